@@ -1,0 +1,200 @@
+/*
+ * sqr.h — C ABI of the MI355X (gfx950) superquadric volume renderer.
+ *
+ * The renderer is SQOcc-R of arXiv 2511.17361 ("SuperQuadricOcc"):
+ * a voxel-indexed volume renderer that turns N superquadric primitives
+ * S_i = {m, s, r, eps, sigma, c} (Sec. 3.1 "SuperQuadrics") into per-pixel
+ * expected depth and semantic renders (Sec. 3.3 "Forward Pass",
+ * Eq. eq:alpha_sem_sq, eq:alpha_composite, eq:depth_sem), and back-propagates
+ * gradients of both renders to every primitive parameter (Sec. 3.3
+ * "Backward Pass").
+ *
+ * Conventions for every entry point below
+ *  - All array pointers are DEVICE pointers, owned by the caller, C-contiguous,
+ *    float32 or int32/int64 as stated.  The library never keeps a pointer
+ *    after a call returns and never allocates device memory inside a call:
+ *    scratch space comes from the caller's `ws` buffer, sized by the matching
+ *    *_workspace() query.
+ *  - Every call is asynchronous on `stream` and performs no host<->device
+ *    synchronisation, so a sequence of calls can be captured into a hipGraph.
+ *  - Arguments are validated on the host before anything is launched; a
+ *    rejected call launches nothing and returns a negative sq_status.
+ *    sq_last_error() then returns a thread-local, human-readable message.
+ *  - Behaviour on NaN/Inf inputs is unspecified (they propagate); scales and
+ *    eps must be > 0.
+ */
+#ifndef SQR_H
+#define SQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sq_status;
+#define SQ_OK              0
+#define SQ_ERR_INVALID    -1  /* bad argument (detected on the host, nothing launched) */
+#define SQ_ERR_CAPACITY   -2  /* workspace or index capacity too small (host-detectable) */
+#define SQ_ERR_HIP        -3  /* a HIP runtime call failed; see sq_last_error() */
+#define SQ_ERR_UNSUPPORTED -4 /* valid request this build does not implement */
+
+#define SQ_MAX_CLASSES 32     /* largest supported number of semantic classes C */
+
+/* Voxel grid (Sec. 3.3 "Preliminary Construction"; bounds and resolution of
+ * Sec. 4.1).  Voxel (ix,iy,iz) covers [lo + i*voxel, lo + (i+1)*voxel) per axis
+ * (half-open; the upper face is outside).  The linear voxel id used by the
+ * index ("hashing" of the paper) is v = (ix*dims[1] + iy)*dims[2] + iz.
+ * nv is the neighbourhood half-width N_v: primitive k is listed in every voxel
+ * v with max_axis |v - c_k| <= nv, where c_k is the voxel containing m_k. */
+typedef struct {
+    float   lo[3];
+    float   voxel;
+    int32_t dims[3];
+    int32_t nv;
+} sq_grid;
+
+/* Superquadric -> voxel CSR lists: the paper's V_n (counts), V_f (offsets,
+ * exclusive prefix sum of counts) and V_sq (ids).  counts/offsets hold
+ * dims[0]*dims[1]*dims[2] int32 each; ids holds `capacity` int32.  Within each
+ * voxel the ids are strictly ascending.  *total (one device int64) receives
+ * E = sum(counts).  If E > capacity, ids holds only the entries below
+ * `capacity` and the index must not be used (check *total after a sync). */
+typedef struct {
+    int32_t* counts;
+    int32_t* offsets;
+    int32_t* ids;
+    int64_t  capacity;
+    int64_t* total;
+} sq_index;
+
+/* N primitives (Sec. 3.1): means [n,3] (m), quats [n,4] (r, stored w,x,y,z,
+ * need not be unit: the renderer uses r/|r|, Hamilton convention, and maps a
+ * point to the local frame as x_S = R(r/|r|) (x - m)), scales [n,3]
+ * (s_x,s_y,s_z > 0), eps [n,2] (eps1, eps2 > 0), opacity [n] (sigma),
+ * logits [n,C] (c).  1 <= n_classes <= SQ_MAX_CLASSES. */
+typedef struct {
+    int32_t      n;
+    int32_t      n_classes;
+    const float* means;
+    const float* quats;
+    const float* scales;
+    const float* eps;
+    const float* opacity;
+    const float* logits;
+} sq_prims;
+
+/* Rays r(t) = o + t d, one per pixel: origins/dirs [n_cams,H,W,3], |d| = 1.
+ * The flat ray id is (cam*H + y)*W + x. */
+typedef struct {
+    int32_t      n_cams;
+    int32_t      height;
+    int32_t      width;
+    const float* origins;
+    const float* dirs;
+} sq_rays;
+
+/* L uniformly spaced samples in [t_near, t_far], endpoints included
+ * (Sec. 3.3 "Preliminary Construction"): t_j = t_near + j*delta with
+ * delta = (t_far - t_near)/(L-1) (t_0 = t_near if L == 1).  Sample depths,
+ * sample points and their voxels are computed in float32 with every op
+ * correctly rounded and no fused multiply-add:
+ *   t_j = fl(t_near + fl(j*delta)), x_j = fl(o + fl(t_j*d)),
+ *   i = floor(fl(fl(x_j - lo) * fl(1/voxel))).
+ * ckpt_every (K) is the transmittance-checkpoint spacing used by the
+ * differentiable forward and the backward; 0 = no checkpoints.
+ * Requires L >= 1 and 0 <= t_near < t_far (t_near <= t_far if L == 1). */
+typedef struct {
+    int32_t n_samples;
+    float   t_near;
+    float   t_far;
+    int32_t ckpt_every;
+} sq_march;
+
+/* Gradient outputs (overwritten, not accumulated), shaped like sq_prims. */
+typedef struct {
+    float* means;    /* [n,3] */
+    float* quats;    /* [n,4] */
+    float* scales;   /* [n,3] */
+    float* eps;      /* [n,2] */
+    float* opacity;  /* [n]   */
+    float* logits;   /* [n,C] */
+} sq_grads;
+
+/* Kernel launch choices (ray-tile width in pixels: 4, 8 or 16; the tile is
+ * 64 pixels, one wavefront; chunk = backward checkpoint spacing).  Passing
+ * NULL to the calls below uses the defaults of sq_default_tuning(). */
+typedef struct {
+    int32_t tile_w;
+    int32_t waves_per_block;
+} sq_tuning;
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* sq_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int32_t sq_version(void);
+
+/* Defaults for sq_tuning. */
+sq_tuning sq_default_tuning(void);
+
+/* Upper bound of E for n primitives on this grid:
+ * n * prod_axis min(2*nv + 1, dims[axis]).  Host-only, no launch. */
+int64_t sq_index_capacity_bound(const sq_grid* grid, int32_t n);
+
+/* Bytes of workspace sq_build_index needs (host-only). */
+size_t sq_build_index_workspace(const sq_grid* grid, int32_t n);
+
+/* Build the superquadric -> voxel lists (Sec. 3.3 "Preliminary Construction":
+ * per-primitive cubic neighbourhood V_c hashed into V_sq, V_f, V_n).
+ * Deterministic: the output is a pure function of (grid, means).
+ * Reads prims->means only.  Writes idx->counts, offsets, ids (< capacity)
+ * and *idx->total. */
+sq_status sq_build_index(const sq_grid* grid, const sq_prims* prims, sq_index* idx,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Bytes of workspace sq_render_fwd / sq_render_bwd need (host-only). */
+size_t sq_render_workspace(const sq_grid* grid, const sq_prims* prims,
+                           const sq_rays* rays, const sq_march* march);
+
+/* Forward render (Sec. 3.3 "Forward Pass").  Per ray, samples front to back;
+ * a sample outside the grid or in a voxel with V_n = 0 is skipped; otherwise
+ *   a_j = sum_{k in Q(v_j)} p_o(x_j, S_k) sigma_k,  alpha_j = min(1, a_j),
+ *   s_j = sum_k p_o(x_j, S_k) c_k                     (Eq. eq:alpha_sem_sq)
+ *   w_j = T_j alpha_j, T_{j+1} = T_j (1 - alpha_j)     (Eq. eq:alpha_composite)
+ *   depth = sum_j w_j t_j, sem = sum_j w_j s_j         (Eq. eq:depth_sem)
+ * with p_o(x, S) = exp(-f(x_S)) (Eq. eq:sq_occupancy_prob) and
+ * f = (|u|^(2/e2) + |v|^(2/e2))^(e2/e1) + |w|^(2/e1), (u,v,w) = x_S / s.
+ * Outputs: depth [n_cams,H,W], sem [n_cams,C,H,W], probs (nullable;
+ * softmax over classes of sem) [n_cams,C,H,W], t_final (T_L) [n_cams,H,W],
+ * ckpt (nullable; needs march->ckpt_every > 0) [ceil(L/K), n_cams*H*W]:
+ * ckpt[c][ray] = T at sample c*K.  `stats` (nullable, 4 device int64,
+ * accumulated) counts non-empty in-grid samples, listed (sample, primitive)
+ * pairs, pairs not culled, and rays; when non-NULL a counting variant of the
+ * kernel runs.  A pair is culled only where float32 exp(-f) is exactly 0. */
+sq_status sq_render_fwd(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
+                        const sq_rays* rays, const sq_march* march,
+                        float* depth, float* sem, float* probs, float* t_final, float* ckpt,
+                        int64_t* stats, const sq_tuning* tuning,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward of sq_render_fwd (Sec. 3.3 "Backward Pass") for upstream gradients
+ * g_depth [n_cams,H,W] and g_sem [n_cams,C,H,W] (either may be NULL = zero).
+ * Needs the checkpoints `ckpt` written by sq_render_fwd with the same
+ * arguments and march->ckpt_every in {4, 8, 16}.  The ray march is replayed
+ * back to front chunk by chunk from the checkpoints; nothing per sample is
+ * stored.  Writes (overwrites) every array of `grads`.  Gradients are summed
+ * with float atomics, so the last bits depend on scheduling order. */
+sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
+                        const sq_rays* rays, const sq_march* march,
+                        const float* ckpt, const float* g_depth, const float* g_sem,
+                        const sq_grads* grads, const sq_tuning* tuning,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQR_H */

@@ -1,0 +1,105 @@
+"""ctypes binding of libsqr.so (the C ABI declared in include/sqr.h).
+
+Argument marshalling only: every step of the renderer runs in the HIP
+library.  Loading fails loudly when the library has not been built; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsqr.so")
+
+SQ_OK = 0
+SQ_ERR_INVALID = -1
+SQ_ERR_CAPACITY = -2
+SQ_ERR_HIP = -3
+SQ_ERR_UNSUPPORTED = -4
+SQ_MAX_CLASSES = 32
+
+EXPORTED = [
+    "sq_last_error", "sq_version", "sq_default_tuning", "sq_index_capacity_bound",
+    "sq_build_index_workspace", "sq_build_index", "sq_render_workspace", "sq_render_fwd", "sq_render_bwd",
+]
+
+
+class SqGrid(ct.Structure):
+    _fields_ = [("lo", ct.c_float * 3), ("voxel", ct.c_float), ("dims", ct.c_int32 * 3), ("nv", ct.c_int32)]
+
+
+class SqIndex(ct.Structure):
+    _fields_ = [("counts", ct.c_void_p), ("offsets", ct.c_void_p), ("ids", ct.c_void_p),
+                ("capacity", ct.c_int64), ("total", ct.c_void_p)]
+
+
+class SqPrims(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("n_classes", ct.c_int32), ("means", ct.c_void_p), ("quats", ct.c_void_p),
+                ("scales", ct.c_void_p), ("eps", ct.c_void_p), ("opacity", ct.c_void_p), ("logits", ct.c_void_p)]
+
+
+class SqRays(ct.Structure):
+    _fields_ = [("n_cams", ct.c_int32), ("height", ct.c_int32), ("width", ct.c_int32),
+                ("origins", ct.c_void_p), ("dirs", ct.c_void_p)]
+
+
+class SqMarch(ct.Structure):
+    _fields_ = [("n_samples", ct.c_int32), ("t_near", ct.c_float), ("t_far", ct.c_float),
+                ("ckpt_every", ct.c_int32)]
+
+
+class SqGrads(ct.Structure):
+    _fields_ = [("means", ct.c_void_p), ("quats", ct.c_void_p), ("scales", ct.c_void_p), ("eps", ct.c_void_p),
+                ("opacity", ct.c_void_p), ("logits", ct.c_void_p)]
+
+
+class SqTuning(ct.Structure):
+    _fields_ = [("tile_w", ct.c_int32), ("waves_per_block", ct.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ct.CDLL:
+    """Load libsqr.so once; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2511_17361_amd.build` "
+                           "(or __graft_entry__.build()) first")
+    lib = ct.CDLL(path)
+    P = ct.POINTER
+    lib.sq_last_error.restype = ct.c_char_p
+    lib.sq_version.restype = ct.c_int32
+    lib.sq_default_tuning.restype = SqTuning
+    lib.sq_index_capacity_bound.restype = ct.c_int64
+    lib.sq_index_capacity_bound.argtypes = [P(SqGrid), ct.c_int32]
+    lib.sq_build_index_workspace.restype = ct.c_size_t
+    lib.sq_build_index_workspace.argtypes = [P(SqGrid), ct.c_int32]
+    lib.sq_build_index.restype = ct.c_int32
+    lib.sq_build_index.argtypes = [P(SqGrid), P(SqPrims), P(SqIndex), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_render_workspace.restype = ct.c_size_t
+    lib.sq_render_workspace.argtypes = [P(SqGrid), P(SqPrims), P(SqRays), P(SqMarch)]
+    lib.sq_render_fwd.restype = ct.c_int32
+    lib.sq_render_fwd.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch),
+                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                  P(SqTuning), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_render_bwd.restype = ct.c_int32
+    lib.sq_render_bwd.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch),
+                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, P(SqGrads), P(SqTuning),
+                                  ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    _lib = lib
+    return lib
+
+
+class SqrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sqr status {code}: {msg}")
+        self.code = code
+
+
+def check(code: int) -> None:
+    if code != SQ_OK:
+        raise SqrError(code, load().sq_last_error().decode(errors="replace"))

@@ -1,0 +1,608 @@
+// Forward and backward ray march of the superquadric renderer (gfx950).
+//
+// Mapping: one wavefront = one tile of 64 rays (tile_w x 64/tile_w pixels of
+// one camera).  Rays of a tile are nearly parallel, so at a given sample index
+// most lanes sit in the same voxel.  Per sample the wave walks the distinct
+// voxels of its active lanes one at a time; inside one voxel the primitive id,
+// its prepared record and its logits are wave-uniform and arrive through the
+// scalar data cache, and each lane evaluates p_o at its own sample point.
+// Nothing here is a dense contraction, so there is no MFMA use.
+//
+// Forward (Sec. 3.3 "Forward Pass", Eq. eq:alpha_sem_sq, eq:alpha_composite,
+// eq:depth_sem).  Backward (Sec. 3.3 "Backward Pass"): per ray, chunks of K
+// samples are replayed back to front from the transmittance checkpoints the
+// forward wrote.  Pass 1 recomputes a_j, alpha_j, T_j and
+// G_j = g_D t_j + <g_S, s_j> front to back inside the chunk (kept in LDS);
+// pass 2 walks the chunk back to front carrying
+// Q_j = alpha_j G_j + (1 - alpha_j) Q_{j+1}, so dL/dalpha_j = T_j (G_j - Q_{j+1})
+// needs no division by (1 - alpha) and no per-sample state outside the chunk.
+// Each pair's parameter contributions are summed across the wave by a
+// transposing butterfly and land in the per-primitive accumulator with one
+// lane-parallel float atomic per pair.
+#include "sqr_device.h"
+#include "sqr_internal.h"
+
+#include <algorithm>
+
+namespace sqr {
+
+// accumulator row layout (floats per primitive = ACC_ROW(CP))
+constexpr int A_SIG = 0, A_E1 = 1, A_E2 = 2, A_XS = 3, A_R = 6, A_LG = 15;
+template <int CP> struct AccRow { static constexpr int V = A_LG + CP; static constexpr int P = V <= 32 ? 32 : 64; };
+
+int padded_classes(int C) {
+    if (C <= 4) return 4;
+    if (C <= 8) return 8;
+    if (C <= 17) return 17;
+    return 32;
+}
+static int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
+
+// ---------------------------------------------------------------------------
+// Per-primitive preparation
+// ---------------------------------------------------------------------------
+template <int CP>
+__global__ __launch_bounds__(256) void k_prep_records(PrimsDev pr, float* __restrict__ rec,
+                                                      float* __restrict__ lgp) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= pr.n) return;
+    float qw = pr.quats[4 * k + 0], qx = pr.quats[4 * k + 1], qy = pr.quats[4 * k + 2], qz = pr.quats[4 * k + 3];
+    const float qinv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qinv; qx *= qinv; qy *= qinv; qz *= qinv;
+    const float R[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                        2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                        2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+    const float is[3] = {1.0f / pr.scales[3 * k], 1.0f / pr.scales[3 * k + 1], 1.0f / pr.scales[3 * k + 2]};
+    const float e1 = pr.eps[2 * k], e2 = pr.eps[2 * k + 1];
+    float* r = rec + (size_t)k * REC;
+    r[0] = pr.means[3 * k]; r[1] = pr.means[3 * k + 1]; r[2] = pr.means[3 * k + 2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) r[3 + 3 * i + j] = R[3 * i + j] * is[i];
+    r[12] = 2.0f / e2;
+    r[13] = 2.0f / e1;
+    r[14] = e2 / e1;
+    r[15] = pr.opacity[k];
+    // f >= max(|u|,|v|,|w|)^(2/eps1): culled where that bound reaches F_CULL
+    r[16] = exp2f(0.5f * e1 * log2f(F_CULL));
+    r[17] = is[0]; r[18] = is[1]; r[19] = is[2];
+    for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < pr.C ? pr.logits[(size_t)k * pr.C + c] : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry
+// ---------------------------------------------------------------------------
+struct TileMap {
+    int tile_w, tile_h, tiles_x, tiles_y, n_tiles;
+};
+
+struct RayLane {
+    bool valid;
+    int cam, px, py;
+    int64_t ray, pix;
+    float ox, oy, oz, dx, dy, dz;
+};
+
+__device__ __forceinline__ bool map_tile(const TileMap& tm, const RaysDev& rays, RayLane& rl) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = blk * wpb + (threadIdx.x >> 6);
+    if (tile >= tm.n_tiles) return false;
+    const int tpc = tm.tiles_x * tm.tiles_y;
+    rl.cam = tile / tpc;
+    const int rem = tile - rl.cam * tpc;
+    const int ty = rem / tm.tiles_x, tx = rem - ty * tm.tiles_x;
+    rl.px = tx * tm.tile_w + (lane % tm.tile_w);
+    rl.py = ty * tm.tile_h + (lane / tm.tile_w);
+    rl.valid = (rl.px < rays.W) & (rl.py < rays.H);
+    rl.pix = (int64_t)rl.py * rays.W + rl.px;
+    rl.ray = (int64_t)rl.cam * rays.H * rays.W + rl.pix;
+    rl.ox = rl.oy = rl.oz = rl.dx = rl.dy = rl.dz = 0.0f;
+    if (rl.valid) {
+        const float* o = rays.origins + 3 * rl.ray;
+        const float* d = rays.dirs + 3 * rl.ray;
+        rl.ox = o[0]; rl.oy = o[1]; rl.oz = o[2];
+        rl.dx = d[0]; rl.dy = d[1]; rl.dz = d[2];
+    }
+    return true;
+}
+
+struct FwdParams {
+    GridDev g;
+    IndexDev idx;
+    int N, C;
+    const float* rec;
+    const float* lgp;
+    RaysDev rays;
+    MarchDev mr;
+    TileMap tm;
+    float *depth, *sem, *probs, *t_final, *ckpt;
+    int64_t* stats;
+};
+
+// ---------------------------------------------------------------------------
+// Forward
+// ---------------------------------------------------------------------------
+template <int CP, bool CKPT, bool STATS>
+__global__ __launch_bounds__(256) void k_render_fwd(FwdParams P) {
+    RayLane rl;
+    if (!map_tile(P.tm, P.rays, rl)) return;    // whole wavefront
+    const int64_t R = (int64_t)P.rays.n_cams * P.rays.H * P.rays.W;
+    const int32_t* __restrict__ counts = P.idx.counts;
+    const int32_t* __restrict__ offsets = P.idx.offsets;
+    const int32_t* __restrict__ ids = P.idx.ids;
+    const float* __restrict__ rec = P.rec;
+    const float* __restrict__ lgp = P.lgp;
+    const int L = P.mr.L, K = P.mr.K;
+
+    float T = rl.valid ? 1.0f : 0.0f;
+    float D = 0.0f;
+    float S[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) S[c] = 0.0f;
+    bool alive = rl.valid;
+    int64_t st_samples = 0, st_pairs = 0, st_nz = 0;
+
+    SamplePos nxt = pinned_sample(P.g, P.mr.t_near, P.mr.delta, 0, rl.ox, rl.oy, rl.oz, rl.dx, rl.dy, rl.dz);
+    int n_nxt = 0, f_nxt = 0;
+    if (alive && nxt.v >= 0) { n_nxt = counts[nxt.v]; f_nxt = offsets[nxt.v]; }
+
+    for (int j = 0; j < L; ++j) {
+        const SamplePos cur = nxt;
+        const int n = n_nxt, f = f_nxt;
+        if (j + 1 < L) {
+            nxt = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j + 1, rl.ox, rl.oy, rl.oz, rl.dx, rl.dy, rl.dz);
+            n_nxt = 0; f_nxt = 0;
+            if (alive && nxt.v >= 0) { n_nxt = counts[nxt.v]; f_nxt = offsets[nxt.v]; }
+        }
+        if (CKPT && (j % K) == 0 && rl.valid) P.ckpt[(int64_t)(j / K) * R + rl.ray] = T;
+
+        const bool act = alive && (cur.v >= 0) && (n > 0);
+        if (wave_ballot(act) != 0) {
+            float a = 0.0f;
+            float s[CP];
+#pragma unroll
+            for (int c = 0; c < CP; ++c) s[c] = 0.0f;
+            if (STATS && act) { ++st_samples; st_pairs += n; }
+            bool pend = act;
+            uint64_t m;
+            while ((m = wave_ballot(pend)) != 0) {
+                const int leader = __builtin_ctzll(m);
+                const int v0 = readlane_i(cur.v, leader);
+                const int f0 = readlane_i(f, leader);
+                int n0 = readlane_i(n, leader);
+                if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity) n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                const bool mine = pend && (cur.v == v0);
+                if (mine) {
+                    for (int e = 0; e < n0; ++e) {
+                        const int k = ids[f0 + e];
+                        if ((unsigned)k >= (unsigned)P.N) continue;
+                        const float* r = rec + (size_t)k * REC;
+                        const float p = eval_p(r, cur.x, cur.y, cur.z);
+                        if (p != 0.0f) {
+                            if (STATS) ++st_nz;
+                            a = fmaf(p, r[15], a);
+                            const float* lg = lgp + (size_t)k * CP;
+#pragma unroll
+                            for (int c = 0; c < CP; ++c) s[c] = fmaf(p, lg[c], s[c]);
+                        }
+                    }
+                }
+                pend = pend && !mine;
+            }
+            // Eq. eq:alpha_composite and eq:depth_sem
+            const float alpha = fminf(a, 1.0f);
+            const float w = T * alpha;
+            D = fmaf(w, cur.t, D);
+#pragma unroll
+            for (int c = 0; c < CP; ++c) S[c] = fmaf(w, s[c], S[c]);
+            T = T * (1.0f - alpha);
+            alive = alive && (T > 0.0f);
+        }
+        if (wave_ballot(alive) == 0) {
+            // every later sample of this tile is exactly zero
+            if (CKPT && rl.valid)
+                for (int c = j / K + 1; c * K < L; ++c) P.ckpt[(int64_t)c * R + rl.ray] = T;
+            break;
+        }
+    }
+
+    if (rl.valid) {
+        P.depth[rl.ray] = D;
+        P.t_final[rl.ray] = T;
+        const int64_t HW = (int64_t)P.rays.H * P.rays.W;
+        float* semp = P.sem + (int64_t)rl.cam * P.C * HW + rl.pix;
+#pragma unroll
+        for (int c = 0; c < CP; ++c)
+            if (c < P.C) semp[c * HW] = S[c];
+        if (P.probs) {
+            float mx = S[0];
+#pragma unroll
+            for (int c = 1; c < CP; ++c)
+                if (c < P.C) mx = fmaxf(mx, S[c]);
+            float e[CP];
+            float sum = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CP; ++c) {
+                e[c] = c < P.C ? expf(S[c] - mx) : 0.0f;
+                sum += e[c];
+            }
+            const float inv = 1.0f / sum;
+            float* pp = P.probs + (int64_t)rl.cam * P.C * HW + rl.pix;
+#pragma unroll
+            for (int c = 0; c < CP; ++c)
+                if (c < P.C) pp[c * HW] = e[c] * inv;
+        }
+    }
+    if (STATS && rl.valid) {
+        atomicAdd((unsigned long long*)&P.stats[0], (unsigned long long)st_samples);
+        atomicAdd((unsigned long long*)&P.stats[1], (unsigned long long)st_pairs);
+        atomicAdd((unsigned long long*)&P.stats[2], (unsigned long long)st_nz);
+        atomicAdd((unsigned long long*)&P.stats[3], 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+struct BwdParams {
+    GridDev g;
+    IndexDev idx;
+    int N, C;
+    const float* rec;
+    const float* lgp;
+    RaysDev rays;
+    MarchDev mr;
+    TileMap tm;
+    const float *ckpt, *g_depth, *g_sem;
+    float* acc;
+};
+
+// Sum VP values over the 64 lanes of a wavefront.  After the call lane l holds
+// the total of value index (l >> (6 - log2 VP)).
+template <int VP>
+__device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
+    int cnt = VP;
+#pragma unroll
+    for (int dist = 32; dist >= 1; dist >>= 1) {
+        if (cnt > 1) {
+            const int half = cnt >> 1;
+            const bool upper = (lane & dist) != 0;
+#pragma unroll
+            for (int i = 0; i < half; ++i) {
+                const float keep = upper ? x[half + i] : x[i];
+                const float send = upper ? x[i] : x[half + i];
+                x[i] = keep + __shfl_xor(send, dist);
+            }
+            cnt = half;
+        } else {
+            x[0] += __shfl_xor(x[0], dist);
+        }
+    }
+    return x[0];
+}
+
+template <int VP> struct Log2 { static constexpr int v = VP == 64 ? 6 : VP == 32 ? 5 : VP == 16 ? 4 : 0; };
+
+template <int CP>
+__global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
+    extern __shared__ float smem[];   // [wave][4][K][64]
+    RayLane rl;
+    if (!map_tile(P.tm, P.rays, rl)) return;
+    constexpr int VP = AccRow<CP>::P;
+    constexpr int V = AccRow<CP>::V;
+    const int lane = threadIdx.x & 63;
+    const int K = P.mr.K, L = P.mr.L;
+    float* sw = smem + (size_t)(threadIdx.x >> 6) * 4 * K * 64;
+    float* sm_a = sw;                 // a_j
+    float* sm_T = sw + K * 64;        // T_j
+    float* sm_G = sw + 2 * K * 64;    // G_j
+    float* sm_v = sw + 3 * K * 64;    // unused slot (keeps the layout 4-wide)
+    (void)sm_v;
+
+    const int64_t R = (int64_t)P.rays.n_cams * P.rays.H * P.rays.W;
+    const int64_t HW = (int64_t)P.rays.H * P.rays.W;
+    const int32_t* __restrict__ counts = P.idx.counts;
+    const int32_t* __restrict__ offsets = P.idx.offsets;
+    const int32_t* __restrict__ ids = P.idx.ids;
+    const float* __restrict__ rec = P.rec;
+    const float* __restrict__ lgp = P.lgp;
+
+    const float gD = (rl.valid && P.g_depth) ? P.g_depth[rl.ray] : 0.0f;
+    float gS[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+        gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[((int64_t)rl.cam * P.C + c) * HW + rl.pix] : 0.0f;
+
+    const int nck = (L + K - 1) / K;
+    float Q = 0.0f;
+    for (int ci = nck - 1; ci >= 0; --ci) {
+        const float Tc = rl.valid ? P.ckpt[(int64_t)ci * R + rl.ray] : 0.0f;
+        if (wave_ballot(Tc > 0.0f) == 0) continue;
+        const int j0 = ci * K;
+        const int jn = min(K, L - j0);
+
+        // ---- pass 1: front to back inside the chunk -------------------------
+        float T = Tc;
+        for (int jj = 0; jj < jn; ++jj) {
+            const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
+                                               rl.dx, rl.dy, rl.dz);
+            int n = 0, f = 0;
+            bool act = (T > 0.0f) && (sp.v >= 0);
+            if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+            float a = 0.0f, G = 0.0f;
+            bool pend = act;
+            uint64_t m;
+            while ((m = wave_ballot(pend)) != 0) {
+                const int leader = __builtin_ctzll(m);
+                const int v0 = readlane_i(sp.v, leader);
+                const int f0 = readlane_i(f, leader);
+                int n0 = readlane_i(n, leader);
+                if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity) n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                const bool mine = pend && (sp.v == v0);
+                if (mine) {
+                    for (int e = 0; e < n0; ++e) {
+                        const int k = ids[f0 + e];
+                        if ((unsigned)k >= (unsigned)P.N) continue;
+                        const float* r = rec + (size_t)k * REC;
+                        const float p = eval_p(r, sp.x, sp.y, sp.z);
+                        if (p != 0.0f) {
+                            a = fmaf(p, r[15], a);
+                            const float* lg = lgp + (size_t)k * CP;
+                            float gam = 0.0f;
+#pragma unroll
+                            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+                            G = fmaf(p, gam, G);
+                        }
+                    }
+                }
+                pend = pend && !mine;
+            }
+            sm_a[jj * 64 + lane] = a;
+            sm_T[jj * 64 + lane] = T;
+            sm_G[jj * 64 + lane] = fmaf(gD, sp.t, G);
+            T = T * (1.0f - fminf(a, 1.0f));
+        }
+
+        // ---- pass 2: back to front, per-pair adjoint -------------------------
+        for (int jj = jn - 1; jj >= 0; --jj) {
+            const float a = sm_a[jj * 64 + lane];
+            const float Tj = sm_T[jj * 64 + lane];
+            const float G = sm_G[jj * 64 + lane];
+            const float alpha = fminf(a, 1.0f);
+            const float dalpha = Tj * (G - Q);
+            Q = fmaf(alpha, G, (1.0f - alpha) * Q);
+            const float da = (a < 1.0f) ? dalpha : 0.0f;
+            const float w = Tj * alpha;
+            // (sigma_k = 0 with p > 0 still gives dL/dsigma_k = da p, so a == 0 is not a skip)
+            const bool live = (Tj > 0.0f) && ((da != 0.0f) || (w != 0.0f));
+            if (wave_ballot(live) == 0) continue;
+
+            const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
+                                               rl.dx, rl.dy, rl.dz);
+            int n = 0, f = 0;
+            bool act = live && (sp.v >= 0);
+            if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+            bool pend = act;
+            uint64_t m;
+            while ((m = wave_ballot(pend)) != 0) {
+                const int leader = __builtin_ctzll(m);
+                const int v0 = readlane_i(sp.v, leader);
+                const int f0 = readlane_i(f, leader);
+                int n0 = readlane_i(n, leader);
+                if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity) n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                const bool mine = pend && (sp.v == v0);
+                for (int e = 0; e < n0; ++e) {
+                    const int k = ids[f0 + e];
+                    if ((unsigned)k >= (unsigned)P.N) continue;
+                    const float* r = rec + (size_t)k * REC;
+                    const float* lg = lgp + (size_t)k * CP;
+                    float x[VP];
+#pragma unroll
+                    for (int i = 0; i < VP; ++i) x[i] = 0.0f;
+                    bool any = false;
+                    float wp = 0.0f;
+                    if (mine) {
+                        PairEval ev;
+                        float dd[3];
+                        if (eval_pair(r, sp.x, sp.y, sp.z, dd, ev) && ev.p > 0.0f) {
+                            any = true;
+                            const float a_ = r[12], b_ = r[13], e_ = r[14], sig = r[15];
+                            float gam = 0.0f;
+#pragma unroll
+                            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+                            const float dp = fmaf(da, sig, w * gam);
+                            const float df = -ev.p * dp;
+                            const float invA = ev.A > 0.0f ? hw_rcp(ev.A) : 0.0f;
+                            const float cu = df * e_ * a_ * ev.B * invA;
+                            const float gu = ev.u != 0.0f ? cu * ev.X * hw_rcp(ev.u) : 0.0f;
+                            const float gv = ev.v != 0.0f ? cu * ev.Y * hw_rcp(ev.v) : 0.0f;
+                            const float gw = ev.w != 0.0f ? df * b_ * ev.Z * hw_rcp(ev.w) : 0.0f;
+                            const float gx0 = gu * r[17], gx1 = gv * r[18], gx2 = gw * r[19];
+                            const float lnA = ev.A > 0.0f ? ev.lA * LN2 : 0.0f;
+                            const float XlU = ev.X > 0.0f ? ev.X * ev.lu * LN2 : 0.0f;
+                            const float YlV = ev.Y > 0.0f ? ev.Y * ev.lv * LN2 : 0.0f;
+                            const float ZlW = ev.Z > 0.0f ? ev.Z * ev.lw * LN2 : 0.0f;
+                            const float dfde1 = -0.5f * e_ * b_ * ev.B * lnA - 0.5f * b_ * b_ * ZlW;
+                            const float dfde2 = 0.5f * e_ * a_ * ev.B * (lnA - a_ * (XlU + YlV) * invA);
+                            x[A_SIG] = da * ev.p;
+                            x[A_E1] = df * dfde1;
+                            x[A_E2] = df * dfde2;
+                            x[A_XS + 0] = gx0; x[A_XS + 1] = gx1; x[A_XS + 2] = gx2;
+                            x[A_R + 0] = gx0 * dd[0]; x[A_R + 1] = gx0 * dd[1]; x[A_R + 2] = gx0 * dd[2];
+                            x[A_R + 3] = gx1 * dd[0]; x[A_R + 4] = gx1 * dd[1]; x[A_R + 5] = gx1 * dd[2];
+                            x[A_R + 6] = gx2 * dd[0]; x[A_R + 7] = gx2 * dd[1]; x[A_R + 8] = gx2 * dd[2];
+                            wp = w * ev.p;
+                        }
+                    }
+                    if (wave_ballot(any) == 0) continue;
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) x[A_LG + c] = wp * gS[c];
+                    const float tot = transpose_reduce<VP>(x, lane);
+                    constexpr int shift = 6 - Log2<VP>::v;
+                    const int vi = lane >> shift;
+                    if (((lane & ((1 << shift) - 1)) == 0) && vi < V && (vi < A_LG || vi - A_LG < P.C))
+                        atomicAdd(P.acc + (size_t)k * VP + vi, tot);
+                }
+                pend = pend && !mine;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: accumulator row -> parameter gradients
+//   g_m = -R^T sum(g_xs);  g_s_i = -(1/s_i) [G_R R^T]_ii  (G_R = sum g_xs (x-m)^T)
+//   g_q = (I - q^ q^T)/|q| * sum_ij G_R_ij dR_ij/dq^
+// ---------------------------------------------------------------------------
+template <int CP>
+__global__ __launch_bounds__(256) void k_finalize(PrimsDev pr, const float* __restrict__ acc, float* g_means,
+                                                  float* g_quats, float* g_scales, float* g_eps, float* g_opacity,
+                                                  float* g_logits) {
+    constexpr int VP = AccRow<CP>::P;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= pr.n) return;
+    const float* a = acc + (size_t)k * VP;
+    const float q0 = pr.quats[4 * k], q1 = pr.quats[4 * k + 1], q2 = pr.quats[4 * k + 2], q3 = pr.quats[4 * k + 3];
+    const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const float w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+    const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
+                        2.f * (x * y + w * z), 1.f - 2.f * (x * x + z * z), 2.f * (y * z - w * x),
+                        2.f * (x * z - w * y), 2.f * (y * z + w * x), 1.f - 2.f * (x * x + y * y)};
+    const float* gx = a + A_XS;
+    const float* G = a + A_R;
+    for (int i = 0; i < 3; ++i) g_means[3 * k + i] = -(R[i] * gx[0] + R[3 + i] * gx[1] + R[6 + i] * gx[2]);
+    for (int i = 0; i < 3; ++i) {
+        const float d = G[3 * i] * R[3 * i] + G[3 * i + 1] * R[3 * i + 1] + G[3 * i + 2] * R[3 * i + 2];
+        g_scales[3 * k + i] = -d / pr.scales[3 * k + i];
+    }
+    // sum_ij G_ij dR_ij/dq^ for the Hamilton matrix above
+    const float gw = -2.f * z * G[1] + 2.f * y * G[2] + 2.f * z * G[3] - 2.f * x * G[5] - 2.f * y * G[6] +
+                     2.f * x * G[7];
+    const float gxq = 2.f * y * G[1] + 2.f * z * G[2] + 2.f * y * G[3] - 4.f * x * G[4] - 2.f * w * G[5] +
+                      2.f * z * G[6] + 2.f * w * G[7] - 4.f * x * G[8];
+    const float gy = -4.f * y * G[0] + 2.f * x * G[1] + 2.f * w * G[2] + 2.f * x * G[3] + 2.f * z * G[5] -
+                     2.f * w * G[6] + 2.f * z * G[7] - 4.f * y * G[8];
+    const float gz = -4.f * z * G[0] - 2.f * w * G[1] + 2.f * x * G[2] + 2.f * w * G[3] - 4.f * z * G[4] +
+                     2.f * y * G[5] + 2.f * x * G[6] + 2.f * y * G[7];
+    const float dot = w * gw + x * gxq + y * gy + z * gz;
+    g_quats[4 * k + 0] = (gw - w * dot) / qn;
+    g_quats[4 * k + 1] = (gxq - x * dot) / qn;
+    g_quats[4 * k + 2] = (gy - y * dot) / qn;
+    g_quats[4 * k + 3] = (gz - z * dot) / qn;
+    g_eps[2 * k] = a[A_E1];
+    g_eps[2 * k + 1] = a[A_E2];
+    g_opacity[k] = a[A_SIG];
+    for (int c = 0; c < pr.C; ++c) g_logits[(size_t)k * pr.C + c] = a[A_LG + c];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+size_t render_workspace_bytes(int n, int C) {
+    const int CP = padded_classes(C);
+    return align_up((size_t)n * REC * sizeof(float)) + align_up((size_t)n * CP * sizeof(float)) +
+           align_up((size_t)n * acc_row(CP) * sizeof(float));
+}
+
+struct WsLayout {
+    float *rec, *lgp, *acc;
+};
+static WsLayout carve(void* ws, int n, int C) {
+    const int CP = padded_classes(C);
+    char* p = (char*)ws;
+    WsLayout l;
+    l.rec = (float*)p; p += align_up((size_t)n * REC * sizeof(float));
+    l.lgp = (float*)p; p += align_up((size_t)n * CP * sizeof(float));
+    l.acc = (float*)p;
+    return l;
+}
+
+static TileMap make_tiles(const RaysDev& rays, const TuneDev& tune) {
+    TileMap tm;
+    tm.tile_w = tune.tile_w;
+    tm.tile_h = 64 / tune.tile_w;
+    tm.tiles_x = (rays.W + tm.tile_w - 1) / tm.tile_w;
+    tm.tiles_y = (rays.H + tm.tile_h - 1) / tm.tile_h;
+    tm.n_tiles = rays.n_cams * tm.tiles_x * tm.tiles_y;
+    return tm;
+}
+
+template <int CP>
+static void prep(const PrimsDev& pr, const WsLayout& l, hipStream_t st) {
+    if (pr.n > 0) hipLaunchKernelGGL(k_prep_records<CP>, dim3((pr.n + 255) / 256), dim3(256), 0, st, pr, l.rec, l.lgp);
+}
+
+template <int CP>
+static void fwd_dispatch(const FwdParams& P, dim3 grid, dim3 block, hipStream_t st) {
+    const bool ck = P.ckpt != nullptr, stt = P.stats != nullptr;
+    if (ck && stt) hipLaunchKernelGGL((k_render_fwd<CP, true, true>), grid, block, 0, st, P);
+    else if (ck) hipLaunchKernelGGL((k_render_fwd<CP, true, false>), grid, block, 0, st, P);
+    else if (stt) hipLaunchKernelGGL((k_render_fwd<CP, false, true>), grid, block, 0, st, P);
+    else hipLaunchKernelGGL((k_render_fwd<CP, false, false>), grid, block, 0, st, P);
+}
+
+hipError_t launch_render_fwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
+                             const MarchDev& mr, float* depth, float* sem, float* probs, float* t_final,
+                             float* ckpt, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st) {
+    const int CP = padded_classes(pr.C);
+    const WsLayout l = carve(ws, pr.n, pr.C);
+    FwdParams P;
+    P.g = g; P.idx = idx; P.N = pr.n; P.C = pr.C; P.rec = l.rec; P.lgp = l.lgp; P.rays = rays; P.mr = mr;
+    P.tm = make_tiles(rays, tune);
+    P.depth = depth; P.sem = sem; P.probs = probs; P.t_final = t_final; P.ckpt = ckpt; P.stats = stats;
+    const int wpb = tune.waves_per_block;
+    const dim3 grid((P.tm.n_tiles + wpb - 1) / wpb), block(64 * wpb);
+    switch (CP) {
+        case 4: prep<4>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<4>(P, grid, block, st); break;
+        case 8: prep<8>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<8>(P, grid, block, st); break;
+        case 17: prep<17>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<17>(P, grid, block, st); break;
+        default: prep<32>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<32>(P, grid, block, st); break;
+    }
+    return hipGetLastError();
+}
+
+template <int CP>
+static void bwd_run(const BwdParams& P, const PrimsDev& pr, const WsLayout& l, int wpb, float* g_means,
+                    float* g_quats, float* g_scales, float* g_eps, float* g_opacity, float* g_logits,
+                    hipStream_t st) {
+    prep<CP>(pr, l, st);
+    const int64_t nacc = (int64_t)pr.n * AccRow<CP>::P;
+    if (nacc > 0) hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((nacc + 255) / 256, 4096)), dim3(256), 0, st,
+                                     l.acc, nacc, 0.0f);
+    if (P.tm.n_tiles) {
+        const dim3 grid((P.tm.n_tiles + wpb - 1) / wpb), block(64 * wpb);
+        const size_t shm = (size_t)wpb * 4 * P.mr.K * 64 * sizeof(float);
+        hipLaunchKernelGGL(k_render_bwd<CP>, grid, block, shm, st, P);
+    }
+    if (pr.n > 0)
+        hipLaunchKernelGGL(k_finalize<CP>, dim3((pr.n + 255) / 256), dim3(256), 0, st, pr, (const float*)l.acc,
+                           g_means, g_quats, g_scales, g_eps, g_opacity, g_logits);
+}
+
+hipError_t launch_render_bwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
+                             const MarchDev& mr, const float* ckpt, const float* g_depth, const float* g_sem,
+                             float* g_means, float* g_quats, float* g_scales, float* g_eps, float* g_opacity,
+                             float* g_logits, const TuneDev& tune, void* ws, hipStream_t st) {
+    const int CP = padded_classes(pr.C);
+    const WsLayout l = carve(ws, pr.n, pr.C);
+    BwdParams P;
+    P.g = g; P.idx = idx; P.N = pr.n; P.C = pr.C; P.rec = l.rec; P.lgp = l.lgp; P.rays = rays; P.mr = mr;
+    P.tm = make_tiles(rays, tune);
+    P.ckpt = ckpt; P.g_depth = g_depth; P.g_sem = g_sem; P.acc = l.acc;
+    const int wpb = tune.waves_per_block;
+    switch (CP) {
+        case 4: bwd_run<4>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+        case 8: bwd_run<8>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+        case 17: bwd_run<17>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+        default: bwd_run<32>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sqr

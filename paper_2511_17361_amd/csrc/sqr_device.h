@@ -1,0 +1,149 @@
+// Device-side building blocks shared by the gfx950 renderer kernels.
+//
+// Everything here runs on CDNA4 wavefronts of 64 lanes.  The renderer maps one
+// wavefront to a tile of 64 rays; per sample, lanes that fall into the same
+// voxel walk that voxel's primitive list together, so the primitive id, its
+// prepared record and its logits are wave-uniform and are fetched with scalar
+// loads into SGPRs (no LDS traffic, no per-lane gathers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sqr {
+
+// ---------------------------------------------------------------------------
+// Prepared per-primitive record (float[REC]), written by k_prep_records.
+//   [0..2]   m                       centre
+//   [3..11]  R' = diag(1/s) R(q/|q|)  row-major, so (u,v,w) = R'(x - m)
+//   [12]     a = 2/eps2   [13] b = 2/eps1   [14] e = eps2/eps1
+//   [15]     sigma
+//   [16]     r_cull: max(|u|,|v|,|w|) >= r_cull  =>  f >= F_CULL
+//   [17..19] 1/s
+// ---------------------------------------------------------------------------
+constexpr int REC = 20;
+constexpr float F_CULL = 110.0f;          // exp(-110) = 1.7e-48: 0 in float32
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float LN2 = 0.6931471805599453f;
+
+// Hardware base-2 transcendentals (v_log_f32 / v_exp_f32).
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ---------------------------------------------------------------------------
+// Pinned float32 discrete decisions: every op correctly rounded, no FMA, so the
+// sample depth, the sample point and its voxel match the oracle bit for bit.
+// ---------------------------------------------------------------------------
+struct GridDev {
+    float lox, loy, loz;
+    float inv;          // fl(1/voxel), computed on the host
+    int X, Y, Z;
+    int nv;
+};
+
+struct SamplePos {
+    float t, x, y, z;
+    int v;              // linear voxel id, or -1 outside the grid
+};
+
+__device__ __forceinline__ SamplePos pinned_sample(const GridDev& g, float t_near, float delta, int j,
+                                                   float ox, float oy, float oz,
+                                                   float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+    SamplePos s;
+    s.t = t_near + (float)j * delta;
+    s.x = ox + s.t * dx;
+    s.y = oy + s.t * dy;
+    s.z = oz + s.t * dz;
+    const float qx = (s.x - g.lox) * g.inv;
+    const float qy = (s.y - g.loy) * g.inv;
+    const float qz = (s.z - g.loz) * g.inv;
+    const bool in = (qx >= 0.0f) & (qx < (float)g.X) & (qy >= 0.0f) & (qy < (float)g.Y) &
+                    (qz >= 0.0f) & (qz < (float)g.Z);
+    // q >= 0 here, so truncation is floor
+    s.v = in ? (((int)qx * g.Y + (int)qy) * g.Z + (int)qz) : -1;
+    return s;
+}
+
+// Centre voxel of a primitive along one axis, bounded before conversion.
+__device__ __forceinline__ int pinned_centre_axis(float m, float lo, float inv, float bound) {
+#pragma clang fp contract(off)
+    float q = (m - lo) * inv;
+    q = fminf(fmaxf(q, -bound), bound);   // NaN -> -bound (covers nothing)
+    return (int)floorf(q);
+}
+
+// ---------------------------------------------------------------------------
+// Pair evaluation p_o(x, S_k) = exp(-f(R(x - m)/s)) (Eq. eq:sq_occupancy_prob).
+// ---------------------------------------------------------------------------
+struct PairEval {
+    float u, v, w;         // canonical coordinates x_S / s
+    float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
+    float X, Y, Z, A, lA, B;
+    float p;
+};
+
+// Returns false when the pair is culled (float32 exp(-f) would be exactly 0).
+__device__ __forceinline__ bool eval_pair(const float* __restrict__ rec, float x, float y, float z,
+                                          float dxyz[3], PairEval& e) {
+    const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
+    dxyz[0] = dx; dxyz[1] = dy; dxyz[2] = dz;
+    e.u = fmaf(rec[3], dx, fmaf(rec[4], dy, rec[5] * dz));
+    e.v = fmaf(rec[6], dx, fmaf(rec[7], dy, rec[8] * dz));
+    e.w = fmaf(rec[9], dx, fmaf(rec[10], dy, rec[11] * dz));
+    const float au = fabsf(e.u), av = fabsf(e.v), aw = fabsf(e.w);
+    const float mx = fmaxf(fmaxf(au, av), aw);
+    if (!(mx < rec[16])) return false;
+    e.lu = hw_log2(au);
+    e.lv = hw_log2(av);
+    e.lw = hw_log2(aw);
+    const float a = rec[12], b = rec[13], ee = rec[14];
+    e.X = hw_exp2(a * e.lu);
+    e.Y = hw_exp2(a * e.lv);
+    e.Z = hw_exp2(b * e.lw);
+    e.A = e.X + e.Y;
+    e.lA = hw_log2(e.A);
+    e.B = hw_exp2(ee * e.lA);
+    const float f = e.B + e.Z;
+    e.p = hw_exp2(-LOG2E * f);
+    return true;
+}
+
+// Forward-only evaluation: returns p (0 when culled).
+__device__ __forceinline__ float eval_p(const float* __restrict__ rec, float x, float y, float z) {
+    const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
+    const float u = fmaf(rec[3], dx, fmaf(rec[4], dy, rec[5] * dz));
+    const float v = fmaf(rec[6], dx, fmaf(rec[7], dy, rec[8] * dz));
+    const float w = fmaf(rec[9], dx, fmaf(rec[10], dy, rec[11] * dz));
+    const float au = fabsf(u), av = fabsf(v), aw = fabsf(w);
+    const float mx = fmaxf(fmaxf(au, av), aw);
+    float p = 0.0f;
+    if (mx < rec[16]) {
+        const float a = rec[12], b = rec[13], ee = rec[14];
+        const float X = hw_exp2(a * hw_log2(au));
+        const float Y = hw_exp2(a * hw_log2(av));
+        const float Z = hw_exp2(b * hw_log2(aw));
+        const float B = hw_exp2(ee * hw_log2(X + Y));
+        p = hw_exp2(-LOG2E * (B + Z));
+    }
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// works on one contiguous range of logical blocks (neighbouring ray tiles share
+// voxel lists and primitive records in that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int per = nb >> 3, rem = nb & 7;
+    const int xcd = b & 7, local = b >> 3;
+    return (xcd < rem) ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+}  // namespace sqr

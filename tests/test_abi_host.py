@@ -1,0 +1,149 @@
+"""Host-only checks of the C ABI library: it loads, exports every symbol
+include/sqr.h declares, and rejects bad arguments before launching anything.
+No compute call here touches a GPU."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+from paper_2511_17361_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "sqr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sq_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    declared = _declared_symbols()
+    assert len(declared) >= 9
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTED) == set(declared)
+
+
+def test_version_and_defaults():
+    lib = L.load()
+    assert lib.sq_version() >= 100
+    t = lib.sq_default_tuning()
+    assert t.tile_w in (4, 8, 16) and 1 <= t.waves_per_block <= 4
+
+
+def _grid(dims=(200, 200, 16), nv=5, voxel=0.4):
+    g = L.SqGrid()
+    for i, v in enumerate((-40.0, -40.0, -1.0)):
+        g.lo[i] = v
+    for i, d in enumerate(dims):
+        g.dims[i] = d
+    g.voxel = voxel
+    g.nv = nv
+    return g
+
+
+def test_capacity_bound_and_workspace():
+    lib = L.load()
+    g = _grid()
+    assert lib.sq_index_capacity_bound(ct.byref(g), 1000) == 1000 * 11 * 11 * 11
+    g2 = _grid(dims=(4, 5, 6), nv=10)
+    assert lib.sq_index_capacity_bound(ct.byref(g2), 3) == 3 * 4 * 5 * 6
+    assert lib.sq_build_index_workspace(ct.byref(g), 6400) >= 6400 * 16
+    bad = _grid(nv=-1)
+    assert lib.sq_index_capacity_bound(ct.byref(bad), 10) == -1
+
+
+def _march(L_=100, tn=0.1, tf=45.0, K=0):
+    m = L.SqMarch()
+    m.n_samples, m.t_near, m.t_far, m.ckpt_every = L_, tn, tf, K
+    return m
+
+
+FAKE = 0x1000   # never dereferenced: every call below must fail validation first
+
+
+def _prims(n=10, C=17):
+    p = L.SqPrims()
+    p.n, p.n_classes = n, C
+    for f in ("means", "quats", "scales", "eps", "opacity", "logits"):
+        setattr(p, f, FAKE)
+    return p
+
+
+def _rays():
+    r = L.SqRays()
+    r.n_cams, r.height, r.width = 1, 8, 8
+    r.origins = FAKE
+    r.dirs = FAKE
+    return r
+
+
+def _index():
+    i = L.SqIndex()
+    i.counts = FAKE
+    i.offsets = FAKE
+    i.ids = FAKE
+    i.capacity = 100
+    i.total = FAKE
+    return i
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda a: setattr(a["grid"], "voxel", 0.0), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["grid"], "nv", -2), L.SQ_ERR_INVALID),
+    (lambda a: a["grid"].dims.__setitem__(1, 0), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["prims"], "n_classes", 33), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["prims"], "n_classes", 0), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["prims"], "n", -1), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["prims"], "opacity", None), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["march"], "n_samples", 0), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["march"], "t_far", 0.05), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["march"], "t_near", -1.0), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["rays"], "dirs", None), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["index"], "counts", None), L.SQ_ERR_INVALID),
+    (lambda a: a.__setitem__("ws_bytes", 16), L.SQ_ERR_CAPACITY),
+    (lambda a: a.__setitem__("tile_w", 5), L.SQ_ERR_INVALID),
+])
+def test_render_fwd_rejects_bad_arguments_without_launch(mutate, code):
+    lib = L.load()
+    args = dict(grid=_grid(), prims=_prims(), rays=_rays(), march=_march(), index=_index(), ws_bytes=1 << 30,
+                tile_w=8)
+    mutate(args)
+    t = L.SqTuning(args["tile_w"], 4)
+    rc = lib.sq_render_fwd(ct.byref(args["grid"]), ct.byref(args["index"]), ct.byref(args["prims"]),
+                           ct.byref(args["rays"]), ct.byref(args["march"]), FAKE, FAKE, None, FAKE, None, None,
+                           ct.byref(t), 0x100000, args["ws_bytes"], None)
+    assert rc == code
+    assert lib.sq_last_error().decode()
+
+
+def test_render_bwd_needs_supported_chunk():
+    lib = L.load()
+    g, p, r, i = _grid(), _prims(), _rays(), _index()
+    gr = L.SqGrads(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE)
+    for K in (0, 3, 32):
+        m = _march(K=K)
+        rc = lib.sq_render_bwd(ct.byref(g), ct.byref(i), ct.byref(p), ct.byref(r), ct.byref(m), FAKE, FAKE, FAKE,
+                               ct.byref(gr), None, 0x100000, 1 << 30, None)
+        assert rc == L.SQ_ERR_INVALID
+    m = _march(K=8)
+    rc = lib.sq_render_bwd(ct.byref(g), ct.byref(i), ct.byref(p), ct.byref(r), ct.byref(m), None, FAKE, FAKE,
+                           ct.byref(gr), None, 0x100000, 1 << 30, None)
+    assert rc == L.SQ_ERR_INVALID and "ckpt" in lib.sq_last_error().decode()
+
+
+def test_build_index_rejects_bad_arguments():
+    lib = L.load()
+    g, p, i = _grid(), _prims(), _index()
+    rc = lib.sq_build_index(ct.byref(g), ct.byref(p), ct.byref(i), 0x100000, 8, None)
+    assert rc == L.SQ_ERR_CAPACITY
+    i.total = None
+    rc = lib.sq_build_index(ct.byref(g), ct.byref(p), ct.byref(i), 0x100000, 1 << 30, None)
+    assert rc == L.SQ_ERR_INVALID
+    big = _grid(dims=(40000, 2, 2))
+    i = _index()
+    rc = lib.sq_build_index(ct.byref(big), ct.byref(p), ct.byref(i), 0x100000, 1 << 30, None)
+    assert rc == L.SQ_ERR_INVALID

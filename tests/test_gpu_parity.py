@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Index: bit-exact.  Forward: depth within 1e-4 relative (1e-5 m below 0.1 m),
+class probabilities within 1e-5 absolute.  Backward: per parameter group
+relative L2 within 1e-3 and per element within 1e-3 |g| + 1e-3 rms(g)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.scenes_small import random_scene, single_prim_scene
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2511_17361_amd import api
+    from tests import gpu_helpers as H
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# index
+# ---------------------------------------------------------------------------
+
+def _index_case(sc):
+    grid, prims, _, _ = H.gpu_scene(sc)
+    idx = api.build_index(grid, prims)
+    torch.cuda.synchronize()
+    e = idx.checked_total()
+    c, o, i, t = oracle.build_index(sc.prims.means, sc.grid)
+    assert e == t
+    np.testing.assert_array_equal(idx.counts.cpu().numpy(), c)
+    np.testing.assert_array_equal(idx.offsets.cpu().numpy(), o)
+    np.testing.assert_array_equal(idx.ids[:e].cpu().numpy(), i)
+    return idx
+
+
+@pytest.mark.parametrize("seed,nv,n", [(0, 5, 64), (1, 0, 30), (2, 2, 200), (3, 40, 9), (4, 5, 0)])
+def test_index_bitexact_small(seed, nv, n):
+    _say("index small", seed, nv, n)
+    sc = random_scene(seed, n=n, nv=nv, dims=(13, 11, 7), voxel=0.5, lo=(-3.0, -2.5, -1.5))
+    # push a few centres outside the grid (boxes partly or fully clipped)
+    if n > 4:
+        sc.prims.means[:4] = np.array([[-5.0, 0, 0], [0, 9.0, 0], [0, 0, -4.2], [30.0, 30.0, 30.0]], np.float32)
+    _index_case(sc)
+
+
+def test_index_bitexact_config0():
+    _index_case(synth.config(0))
+
+
+def test_index_bitexact_config1_and_repeatable():
+    sc = synth.config(1)
+    _say("index config1")
+    idx = _index_case(sc)
+    grid, prims, _, _ = H.gpu_scene(sc)
+    idx2 = api.build_index(grid, prims)
+    torch.cuda.synchronize()
+    assert torch.equal(idx.ids, idx2.ids) and torch.equal(idx.counts, idx2.counts)
+
+
+def test_index_capacity_overflow_is_reported():
+    sc = random_scene(5, n=50, nv=3, dims=(12, 12, 6))
+    grid, prims, _, _ = H.gpu_scene(sc)
+    idx = api.build_index(grid, prims, capacity=100)
+    torch.cuda.synchronize()
+    with pytest.raises(Exception):
+        idx.checked_total()
+    # the kernels wrote nothing beyond the capacity and the true E is reported
+    assert int(idx.total.item()) == oracle.box_volume_total(sc.prims.means, sc.grid)
+
+
+# ---------------------------------------------------------------------------
+# forward
+# ---------------------------------------------------------------------------
+
+def _fwd_case(sc, tuning=None, ray_ids=None, what=""):
+    out, _ = H.run_fwd(sc, tuning=tuning)
+    ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march, ray_ids=ray_ids)
+    if ray_ids is None:
+        H.assert_depth_close(out["depth"], ref["depth"], what)
+        H.assert_probs_close(out["probs"], ref["probs"], what)
+        H.assert_tfinal_close(out["t_final"], ref["t_final"], what)
+    else:
+        H.assert_depth_close(out["depth"].reshape(-1)[ray_ids], ref["depth"], what)
+        H.assert_probs_close(H.flat_sem(out["probs"])[ray_ids], ref["probs"], what)
+        H.assert_tfinal_close(out["t_final"].reshape(-1)[ray_ids], ref["t_final"], what)
+    return out, ref
+
+
+def test_fwd_config0_full():
+    _say("fwd config0")
+    _fwd_case(synth.config(0), what="cfg0")
+
+
+@pytest.mark.parametrize("tile_w,wpb", [(8, 4), (4, 1), (16, 2)])
+@pytest.mark.parametrize("seed,n,C,nv", [(20, 12, 3, 5), (21, 40, 17, 2), (22, 25, 1, 0), (23, 30, 20, 40),
+                                         (24, 18, 32, 3), (25, 15, 8, 5)])
+def test_fwd_small_scenes_ragged(seed, n, C, nv, tile_w, wpb):
+    _say("fwd small", seed, n, C, nv, tile_w, wpb)
+    sc = random_scene(seed, n=n, n_classes=C, nv=nv, width=37, height=23, n_samples=33, opacity_hi=0.7,
+                      dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0)
+    _fwd_case(sc, tuning=api.Tuning(tile_w, wpb), what=f"seed{seed}")
+
+
+def test_fwd_edge_cases():
+    _say("fwd edge: empty scene")
+    sc = random_scene(30, n=0, width=9, height=7)
+    out, _ = H.run_fwd(sc)
+    assert np.all(out["depth"] == 0) and np.all(out["t_final"] == 1) and np.all(out["sem"] == 0)
+    _say("fwd edge: single sample")
+    sc = random_scene(31, n=10, width=9, height=7, n_samples=1)
+    _fwd_case(sc, what="L=1")
+    _say("fwd edge: camera outside the grid looking away")
+    sc = random_scene(32, n=10, width=9, height=7, cam=(0.0, 0.0, 10.0))
+    out, _ = H.run_fwd(sc)
+    assert np.all(out["t_final"] == 1)
+    _say("fwd edge: primitives all outside the grid")
+    sc = random_scene(33, n=10, width=9, height=7)
+    sc.prims.means[:] = np.float32(50.0)
+    out, _ = H.run_fwd(sc)
+    assert np.all(out["depth"] == 0)
+    _say("fwd edge: saturating ellipsoid")
+    sc = single_prim_scene(mean=(0.2, -0.1, 0.0), quat=(0.9, 0.1, -0.3, 0.2), scales=(0.9, 0.6, 0.5),
+                           eps=(1.0, 1.0), opacity=4.48, logits=(0.3, -1.0), yaw=-90.0, cam=(0.0, 3.5, 0.1),
+                           nv=45, dims=(40, 40, 40), lo=(-10.0, -10.0, -10.0), hfov=40.0, width=8, height=6)
+    _fwd_case(sc, what="ellipsoid")
+
+
+def test_fwd_config1_sampled_rays():
+    sc = synth.config(1)
+    rng = np.random.default_rng(0)
+    ids = rng.choice(sc.rays.n_rays, 3000, replace=False)
+    _say("fwd config1")
+    out, _ = _fwd_case(sc, ray_ids=ids, what="cfg1")
+    # a whole ragged window too (several tiles)
+    win = np.arange(352 * 37, 352 * 37 + 352 * 3)
+    ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march, ray_ids=win)
+    H.assert_depth_close(out["depth"].reshape(-1)[win], ref["depth"], "cfg1 window")
+    H.assert_probs_close(H.flat_sem(out["probs"])[win], ref["probs"], "cfg1 window")
+
+
+def test_fwd_config4_sampled_rays():
+    sc = synth.config(4)
+    rng = np.random.default_rng(1)
+    ids = rng.choice(sc.rays.n_rays, 600, replace=False)
+    _say("fwd config4")
+    _fwd_case(sc, ray_ids=ids, what="cfg4")
+
+
+def test_fwd_deterministic_and_ckpt_consistent():
+    sc = synth.config(0)
+    a, _ = H.run_fwd(sc)
+    b, _ = H.run_fwd(sc, ckpt_every=8)
+    for k in ("depth", "sem", "t_final"):
+        assert np.array_equal(a[k], b[k]), k
+    ck = b["ckpt"]
+    assert ck.shape == (4, sc.rays.n_rays)
+    assert np.all(ck[0] == 1.0)
+    assert np.all(np.diff(ck, axis=0) <= 0)
+    assert np.all(ck[-1] >= b["t_final"].reshape(-1))
+
+
+# ---------------------------------------------------------------------------
+# backward
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("K", [4, 8, 16])
+@pytest.mark.parametrize("seed,n,C,opac", [(40, 6, 3, 0.4), (41, 12, 4, 1.0), (42, 20, 17, 0.8), (43, 8, 32, 0.6)])
+def test_bwd_small_scenes(seed, n, C, opac, K):
+    _say("bwd small", seed, n, C, opac, K)
+    sc = random_scene(seed, n=n, n_classes=C, width=19, height=13, n_samples=37, opacity_hi=opac,
+                      dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0)
+    rng = np.random.default_rng(seed)
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, C)
+    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=K)
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    H.assert_grads_close(g, ref, f"seed{seed} K{K}")
+
+
+def test_bwd_config0():
+    sc = synth.config(0)
+    rng = np.random.default_rng(7)
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, sc.prims.n_classes)
+    _say("bwd config0")
+    _, g = H.run_fwd_bwd(sc, g_d, g_s)
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    H.assert_grads_close(g, ref, "cfg0")
+
+
+def test_bwd_config2_sparse_upstream():
+    """Config 2 (config 1 shapes): upstream gradients non-zero on 1500 rays only,
+    so the oracle's gradient is exact while touching those rays alone."""
+    sc = synth.config(2)
+    C = sc.prims.n_classes
+    rng = np.random.default_rng(8)
+    ids = rng.choice(sc.rays.n_rays, 1500, replace=False)
+    g_d = np.zeros(sc.rays.n_rays, np.float32)
+    g_s = np.zeros((sc.rays.n_rays, C), np.float32)
+    g_d[ids] = rng.standard_normal(ids.size).astype(np.float32)
+    g_s[ids] = rng.standard_normal((ids.size, C)).astype(np.float32)
+    cams, Hh, Ww = sc.rays.shape
+    g_d_img = g_d.reshape(cams, Hh, Ww)
+    g_s_img = g_s.reshape(cams, Hh, Ww, C).transpose(0, 3, 1, 2).copy()
+    _say("bwd config2")
+    _, g = H.run_fwd_bwd(sc, g_d_img, g_s_img)
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d[ids], g_s[ids], ray_ids=ids)
+    H.assert_grads_close(g, ref, "cfg2")
