@@ -60,7 +60,8 @@ def parse():
     ap.add_argument("--ckpt-every", type=int, default=8)
     ap.add_argument("--tile-w", type=int, default=8)
     ap.add_argument("--wpb", type=int, default=4)
-    ap.add_argument("--cpu-rays", type=int, default=96, help="rays in the oracle's CPU sample")
+    ap.add_argument("--bwd-mode", type=int, default=0, help="0 auto, 1 sample-major, 2 primitive-major")
+    ap.add_argument("--cpu-rays", type=int, default=4096, help="rays in the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     return ap.parse_args()
@@ -106,7 +107,7 @@ def main():
     rays = api.Rays.from_numpy(sc.rays, dev)
     C = sc.prims.n_classes
     K = args.ckpt_every
-    tune = api.Tuning(args.tile_w, args.wpb)
+    tune = api.Tuning(args.tile_w, args.wpb, args.bwd_mode)
     rng = np.random.default_rng(1)
     g_d_np, g_s_np = synth.upstream_grads(rng, sc.rays, C)
     g_d = torch.from_numpy(g_d_np).to(dev)
@@ -181,7 +182,8 @@ def main():
                                 f"{'x'.join(map(str, sc.grid.dims))} at {sc.grid.voxel} m, N_v={sc.grid.nv}; "
                                 "step = index + forward(ckpt) + backward"),
                    "rays": R, "samples_per_ray": Ls, "superquadrics": sc.prims.n, "classes": C,
-                   "ckpt_every": K, "tile_w": args.tile_w, "waves_per_block": args.wpb},
+                   "ckpt_every": K, "tile_w": args.tile_w, "waves_per_block": args.wpb,
+                   "bwd_mode": args.bwd_mode},
         "fwd_ray_samples_per_s": R * Ls / (t_fwd / 1e3),
         "plain_fwd_ray_samples_per_s": R * Ls / (t_plain / 1e3),
         "rays_per_s_fwd_bwd": R / (ms_step / 1e3),

@@ -123,12 +123,20 @@ typedef struct {
     float* logits;   /* [n,C] */
 } sq_grads;
 
-/* Kernel launch choices (ray-tile width in pixels: 4, 8 or 16; the tile is
- * 64 pixels, one wavefront; chunk = backward checkpoint spacing).  Passing
- * NULL to the calls below uses the defaults of sq_default_tuning(). */
+/* Kernel launch choices.  tile_w: ray-tile width in pixels (4, 8 or 16; a
+ * tile is 64 pixels = one wavefront).  waves_per_block: 1..4.  bwd_mode:
+ * SQ_BWD_AUTO picks the primitive-major backward when it applies
+ * (ckpt_every in {4, 8}, grid within 2047 x 2047 x 511, per-wave id bitmap
+ * within the LDS budget) and the sample-major one otherwise; the other two
+ * values force one of them (forcing primitive-major where it does not apply
+ * returns SQ_ERR_UNSUPPORTED).  Passing NULL uses sq_default_tuning(). */
+#define SQ_BWD_AUTO 0
+#define SQ_BWD_SAMPLE_MAJOR 1
+#define SQ_BWD_PRIMITIVE_MAJOR 2
 typedef struct {
     int32_t tile_w;
     int32_t waves_per_block;
+    int32_t bwd_mode;
 } sq_tuning;
 
 /* Thread-local description of the last failure on this thread ("" if none). */
@@ -173,7 +181,8 @@ size_t sq_render_workspace(const sq_grid* grid, const sq_prims* prims,
  * ckpt[c][ray] = T at sample c*K.  `stats` (nullable, 4 device int64,
  * accumulated) counts non-empty in-grid samples, listed (sample, primitive)
  * pairs, pairs not culled, and rays; when non-NULL a counting variant of the
- * kernel runs.  A pair is culled only where float32 exp(-f) is exactly 0. */
+ * kernel runs.  A pair is culled only where float32 exp(-f) is exactly 0
+ * (f >= 110, detected from max(|u|,|v|,|w|) before any transcendental). */
 sq_status sq_render_fwd(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
                         const sq_rays* rays, const sq_march* march,
                         float* depth, float* sem, float* probs, float* t_final, float* ckpt,
@@ -186,11 +195,14 @@ sq_status sq_render_fwd(const sq_grid* grid, const sq_index* idx, const sq_prims
  * arguments and march->ckpt_every in {4, 8, 16}.  The ray march is replayed
  * back to front chunk by chunk from the checkpoints; nothing per sample is
  * stored.  Writes (overwrites) every array of `grads`.  Gradients are summed
- * with float atomics, so the last bits depend on scheduling order. */
+ * with float atomics, so the last bits depend on scheduling order.
+ * `stats` (nullable, 6 device int64, accumulated) selects a counting variant
+ * that also reports, for the front-to-back recompute pass and for the adjoint
+ * pass: samples visited, listed pairs, pairs not culled. */
 sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
                         const sq_rays* rays, const sq_march* march,
                         const float* ckpt, const float* g_depth, const float* g_sem,
-                        const sq_grads* grads, const sq_tuning* tuning,
+                        const sq_grads* grads, int64_t* stats, const sq_tuning* tuning,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus

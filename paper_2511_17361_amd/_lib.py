@@ -54,8 +54,13 @@ class SqGrads(ct.Structure):
                 ("opacity", ct.c_void_p), ("logits", ct.c_void_p)]
 
 
+SQ_BWD_AUTO = 0
+SQ_BWD_SAMPLE_MAJOR = 1
+SQ_BWD_PRIMITIVE_MAJOR = 2
+
+
 class SqTuning(ct.Structure):
-    _fields_ = [("tile_w", ct.c_int32), ("waves_per_block", ct.c_int32)]
+    _fields_ = [("tile_w", ct.c_int32), ("waves_per_block", ct.c_int32), ("bwd_mode", ct.c_int32)]
 
 
 _lib = None
@@ -88,7 +93,7 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                   P(SqTuning), ct.c_void_p, ct.c_size_t, ct.c_void_p]
     lib.sq_render_bwd.restype = ct.c_int32
     lib.sq_render_bwd.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch),
-                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, P(SqGrads), P(SqTuning),
+                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, P(SqGrads), ct.c_void_p, P(SqTuning),
                                   ct.c_void_p, ct.c_size_t, ct.c_void_p]
     _lib = lib
     return lib

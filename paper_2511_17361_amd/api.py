@@ -135,11 +135,13 @@ class Rays:
 class Tuning:
     tile_w: int = 8
     waves_per_block: int = 4
+    bwd_mode: int = L.SQ_BWD_AUTO
 
     def c(self) -> L.SqTuning:
         t = L.SqTuning()
         t.tile_w = int(self.tile_w)
         t.waves_per_block = int(self.waves_per_block)
+        t.bwd_mode = int(self.bwd_mode)
         return t
 
 
@@ -247,8 +249,10 @@ def render_fwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt_every: 
 
 def render_bwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt: torch.Tensor, ckpt_every: int,
                g_depth: Optional[torch.Tensor], g_sem: Optional[torch.Tensor], tuning: Optional[Tuning] = None,
-               stream=None, ws: Optional[Workspace] = None, out: Optional[dict] = None) -> dict:
-    """sq_render_bwd: gradients of sum(g_depth*depth) + sum(g_sem*sem) w.r.t. the primitives."""
+               stream=None, ws: Optional[Workspace] = None, out: Optional[dict] = None,
+               stats: Optional[torch.Tensor] = None) -> dict:
+    """sq_render_bwd: gradients of sum(g_depth*depth) + sum(g_sem*sem) w.r.t. the primitives.
+    `stats` (6 int64 on the device, accumulated) selects the counting variant."""
     lib = L.load()
     grid, march = Grid.of(grid), March.of(march)
     dev = prims.means.device
@@ -264,6 +268,19 @@ def render_bwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt: torch.
     gd = None if g_depth is None else _f32(g_depth, "g_depth")
     gs = None if g_sem is None else _f32(g_sem, "g_sem")
     L.check(lib.sq_render_bwd(ct.byref(g), ct.byref(ix), ct.byref(p), ct.byref(r), ct.byref(m),
-                              _ptr(ckpt), _ptr(gd), _ptr(gs), ct.byref(gr), ct.byref(t), _ptr(wbuf),
+                              _ptr(ckpt), _ptr(gd), _ptr(gs), ct.byref(gr), _ptr(stats), ct.byref(t), _ptr(wbuf),
                               wbuf.numel(), _stream_handle(stream)))
     return out
+
+
+BWD_STAT_NAMES = ("samples1", "listed1", "eval1", "samples2", "listed2", "eval2")
+
+
+def render_bwd_stats(grid, index: Index, prims: Prims, rays: Rays, march, ckpt, ckpt_every, g_depth, g_sem,
+                     tuning: Optional[Tuning] = None, stream=None, ws: Optional[Workspace] = None) -> dict:
+    """Unit counts of the backward (counting variant of sq_render_bwd)."""
+    st = torch.zeros(6, dtype=torch.int64, device=prims.means.device)
+    render_bwd(grid, index, prims, rays, march, ckpt, ckpt_every, g_depth, g_sem, tuning=tuning, stream=stream,
+               ws=ws, stats=st)
+    vals = st.cpu().tolist()
+    return dict(zip(BWD_STAT_NAMES, vals))

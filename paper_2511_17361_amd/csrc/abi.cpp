@@ -111,8 +111,11 @@ sq_status tuning_of(const sq_tuning* t, sqr::TuneDev& d) {
         return fail(SQ_ERR_INVALID, "tile_w = %d not in {4, 8, 16}", v.tile_w);
     if (v.waves_per_block < 1 || v.waves_per_block > 4)
         return fail(SQ_ERR_INVALID, "waves_per_block = %d not in [1, 4]", v.waves_per_block);
+    if (v.bwd_mode < SQ_BWD_AUTO || v.bwd_mode > SQ_BWD_PRIMITIVE_MAJOR)
+        return fail(SQ_ERR_INVALID, "bwd_mode = %d not in {0, 1, 2}", v.bwd_mode);
     d.tile_w = v.tile_w;
     d.waves_per_block = v.waves_per_block;
+    d.bwd_mode = v.bwd_mode;
     return SQ_OK;
 }
 
@@ -149,6 +152,7 @@ sq_tuning sq_default_tuning(void) {
     sq_tuning t;
     t.tile_w = 8;
     t.waves_per_block = 4;
+    t.bwd_mode = SQ_BWD_AUTO;
     return t;
 }
 
@@ -222,8 +226,8 @@ sq_status sq_render_fwd(const sq_grid* grid, const sq_index* idx, const sq_prims
 
 sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims* prims, const sq_rays* rays,
                         const sq_march* march, const float* ckpt, const float* g_depth, const float* g_sem,
-                        const sq_grads* grads, const sq_tuning* tuning, void* ws, size_t ws_bytes,
-                        hipStream_t stream) {
+                        const sq_grads* grads, int64_t* stats, const sq_tuning* tuning, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
     sq_status s = check_render_common(grid, idx, prims, rays, march, ws, ws_bytes);
     if (s) return s;
     if (!(march->ckpt_every == 4 || march->ckpt_every == 8 || march->ckpt_every == 16))
@@ -236,9 +240,13 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
         return fail(SQ_ERR_INVALID, "a gradient output array is NULL");
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
+    if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
+        !sqr::bwd_primitive_major_ok(to_dev(grid), prims->n, march->ckpt_every, tune.waves_per_block))
+        return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply (ckpt_every %d, n %d)",
+                    march->ckpt_every, prims->n);
     const hipError_t e = sqr::launch_render_bwd(to_dev(grid), to_dev(idx), to_dev(prims), to_dev(rays),
                                                 to_dev(march), ckpt, g_depth, g_sem, grads->means, grads->quats,
-                                                grads->scales, grads->eps, grads->opacity, grads->logits, tune, ws,
+                                                grads->scales, grads->eps, grads->opacity, grads->logits, stats, tune, ws,
                                                 stream);
     return hip_status(e, "sq_render_bwd");
 }

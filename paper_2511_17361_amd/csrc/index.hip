@@ -26,21 +26,9 @@ __global__ __launch_bounds__(256) void k_prep_boxes(const float* __restrict__ me
                                                     int4* __restrict__ boxes) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const int dims[3] = {g.X, g.Y, g.Z};
-    const float lo[3] = {g.lox, g.loy, g.loz};
-    int packed[3];
-    bool empty = false;
-    for (int ax = 0; ax < 3; ++ax) {
-        const float bound = (float)(max(max(g.X, g.Y), g.Z) + g.nv + 2);
-        const int c = pinned_centre_axis(means[3 * k + ax], lo[ax], g.inv, bound);
-        const int blo = max(c - g.nv, 0);
-        const int bhi = min(c + g.nv, dims[ax] - 1);
-        if (blo > bhi) empty = true;
-        packed[ax] = (blo & 0xffff) | (bhi << 16);
-    }
-    // an empty box is stored as lo = 1, hi = 0 on every axis: no voxel matches
-    const int none = 1;
-    boxes[k] = empty ? make_int4(none, none, none, 0) : make_int4(packed[0], packed[1], packed[2], 1);
+    int b[3];
+    prim_box(g, means[3 * k], means[3 * k + 1], means[3 * k + 2], b);
+    boxes[k] = make_int4(b[0], b[1], b[2], 0);
 }
 
 __device__ __forceinline__ bool box_has(int bx, int i) {

@@ -42,7 +42,7 @@ static int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
 // Per-primitive preparation
 // ---------------------------------------------------------------------------
 template <int CP>
-__global__ __launch_bounds__(256) void k_prep_records(PrimsDev pr, float* __restrict__ rec,
+__global__ __launch_bounds__(256) void k_prep_records(PrimsDev pr, GridDev g, float* __restrict__ rec,
                                                       float* __restrict__ lgp) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= pr.n) return;
@@ -65,6 +65,10 @@ __global__ __launch_bounds__(256) void k_prep_records(PrimsDev pr, float* __rest
     // f >= max(|u|,|v|,|w|)^(2/eps1): culled where that bound reaches F_CULL
     r[16] = exp2f(0.5f * e1 * log2f(F_CULL));
     r[17] = is[0]; r[18] = is[1]; r[19] = is[2];
+    int box[3];
+    prim_box(g, r[0], r[1], r[2], box);
+    r[20] = __int_as_float(box[0]); r[21] = __int_as_float(box[1]); r[22] = __int_as_float(box[2]);
+    r[23] = 0.0f;
     for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < pr.C ? pr.logits[(size_t)k * pr.C + c] : 0.0f;
 }
 
@@ -184,8 +188,8 @@ __global__ __launch_bounds__(256) void k_render_fwd(FwdParams P) {
                         if ((unsigned)k >= (unsigned)P.N) continue;
                         const float* r = rec + (size_t)k * REC;
                         const float p = eval_p(r, cur.x, cur.y, cur.z);
+                        if (STATS && pair_kept(r, cur.x, cur.y, cur.z)) ++st_nz;
                         if (p != 0.0f) {
-                            if (STATS) ++st_nz;
                             a = fmaf(p, r[15], a);
                             const float* lg = lgp + (size_t)k * CP;
 #pragma unroll
@@ -261,35 +265,13 @@ struct BwdParams {
     TileMap tm;
     const float *ckpt, *g_depth, *g_sem;
     float* acc;
+    int64_t* stats;
+    int bitmap_words;   // per-wave bitmap size of the primitive-major path
 };
-
-// Sum VP values over the 64 lanes of a wavefront.  After the call lane l holds
-// the total of value index (l >> (6 - log2 VP)).
-template <int VP>
-__device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
-    int cnt = VP;
-#pragma unroll
-    for (int dist = 32; dist >= 1; dist >>= 1) {
-        if (cnt > 1) {
-            const int half = cnt >> 1;
-            const bool upper = (lane & dist) != 0;
-#pragma unroll
-            for (int i = 0; i < half; ++i) {
-                const float keep = upper ? x[half + i] : x[i];
-                const float send = upper ? x[i] : x[half + i];
-                x[i] = keep + __shfl_xor(send, dist);
-            }
-            cnt = half;
-        } else {
-            x[0] += __shfl_xor(x[0], dist);
-        }
-    }
-    return x[0];
-}
 
 template <int VP> struct Log2 { static constexpr int v = VP == 64 ? 6 : VP == 32 ? 5 : VP == 16 ? 4 : 0; };
 
-template <int CP>
+template <int CP, bool STATS>
 __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
     extern __shared__ float smem[];   // [wave][4][K][64]
     RayLane rl;
@@ -321,6 +303,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
 
     const int nck = (L + K - 1) / K;
     float Q = 0.0f;
+    int64_t st[6] = {0, 0, 0, 0, 0, 0};   // samples, listed, evaluated pairs of pass 1 and of pass 2
     for (int ci = nck - 1; ci >= 0; --ci) {
         const float Tc = rl.valid ? P.ckpt[(int64_t)ci * R + rl.ray] : 0.0f;
         if (wave_ballot(Tc > 0.0f) == 0) continue;
@@ -335,6 +318,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
             int n = 0, f = 0;
             bool act = (T > 0.0f) && (sp.v >= 0);
             if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+            if (STATS && act) { st[0] += 1; st[1] += n; }
             float a = 0.0f, G = 0.0f;
             bool pend = act;
             uint64_t m;
@@ -351,6 +335,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                         if ((unsigned)k >= (unsigned)P.N) continue;
                         const float* r = rec + (size_t)k * REC;
                         const float p = eval_p(r, sp.x, sp.y, sp.z);
+                        if (STATS && pair_kept(r, sp.x, sp.y, sp.z)) st[2] += 1;
                         if (p != 0.0f) {
                             a = fmaf(p, r[15], a);
                             const float* lg = lgp + (size_t)k * CP;
@@ -388,6 +373,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
             int n = 0, f = 0;
             bool act = live && (sp.v >= 0);
             if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+            if (STATS && act) { st[3] += 1; st[4] += n; }
             bool pend = act;
             uint64_t m;
             while ((m = wave_ballot(pend)) != 0) {
@@ -410,7 +396,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                     if (mine) {
                         PairEval ev;
                         float dd[3];
-                        if (eval_pair(r, sp.x, sp.y, sp.z, dd, ev) && ev.p > 0.0f) {
+                        const bool kept = eval_pair(r, sp.x, sp.y, sp.z, dd, ev);
+                        if (STATS && kept) st[5] += 1;
+                        if (kept && ev.p > 0.0f) {
                             any = true;
                             const float a_ = r[12], b_ = r[13], e_ = r[14], sig = r[15];
                             float gam = 0.0f;
@@ -453,6 +441,267 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
             }
         }
     }
+    if (STATS && rl.valid)
+        for (int i = 0; i < 6; ++i) atomicAdd((unsigned long long*)&P.stats[i], (unsigned long long)st[i]);
+}
+
+
+// ---------------------------------------------------------------------------
+// Backward, primitive-major inside a chunk (default path)
+//
+// Per wavefront and chunk of KC samples:
+//  1. the ids listed in the chunk's voxels are marked in a per-wave LDS bitmap
+//     (one bit per primitive), which enumerates their union in ascending id;
+//  2. pass 1 walks that union: for each primitive k (wave-uniform, record in
+//     SGPRs) every lane tests which of its KC samples lie in k's box
+//     (= k is listed in the sample's voxel) and accumulates a_j += p sigma_k,
+//     G_j += p <g_S, c_k>; summation order per sample is ascending id, as in
+//     the forward;
+//  3. compositing and its adjoint run per lane over the KC samples;
+//  4. pass 2 walks the union again: each lane sums the contributions of all
+//     its samples to k's parameters in registers, then the wave reduces them
+//     once per (chunk, primitive) and lands them with one lane-parallel float
+//     atomic.  Compared with one reduction per (sample, primitive), the
+//     reductions and atomics shrink by the number of chunk samples that share
+//     a primitive.
+// ---------------------------------------------------------------------------
+constexpr int PV_BITS_X = 11, PV_BITS_Y = 11;    // packed voxel: ix | iy << 11 | iz << 22
+constexpr int KM_MAX_XY = (1 << 11) - 1, KM_MAX_Z = (1 << 9) - 1;
+
+__device__ __forceinline__ int pack_voxel(int ix, int iy, int iz) {
+    return ix | (iy << PV_BITS_X) | (iz << (PV_BITS_X + PV_BITS_Y));
+}
+
+// k listed in packed voxel pv (pv < 0: dead sample)?
+__device__ __forceinline__ bool listed_in(int pv, int bx, int by, int bz) {
+    const int ix = pv & ((1 << PV_BITS_X) - 1);
+    const int iy = (pv >> PV_BITS_X) & ((1 << PV_BITS_Y) - 1);
+    const int iz = (int)((unsigned)pv >> (PV_BITS_X + PV_BITS_Y));
+    return (pv >= 0) & in_range(ix, bx) & in_range(iy, by) & in_range(iz, bz);
+}
+
+// Visit the set bits of a per-wave bitmap in ascending order (wave-uniform).
+template <typename F>
+__device__ __forceinline__ void for_each_marked(const uint32_t* bm, int nw, int lane, F&& body) {
+    for (int wb = 0; wb < nw; wb += 64) {
+        const uint32_t word = bm[wb + lane];
+        uint64_t nz = wave_ballot(word != 0u);
+        while (nz) {
+            const int l = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)word, l);
+            while (wv) {
+                const int b = __builtin_ctz(wv);
+                wv &= wv - 1;
+                body(((wb + l) << 5) + b);
+            }
+        }
+    }
+}
+
+template <int CP, int KC, bool STATS>
+__global__ __launch_bounds__(256) void k_render_bwd_km(BwdParams P) {
+    extern __shared__ uint32_t bm_all[];
+    RayLane rl;
+    if (!map_tile(P.tm, P.rays, rl)) return;
+    constexpr int VP = AccRow<CP>::P;
+    constexpr int V = AccRow<CP>::V;
+    const int lane = threadIdx.x & 63;
+    const int nw = P.bitmap_words;
+    uint32_t* bm = bm_all + (size_t)(threadIdx.x >> 6) * nw;
+    const int L = P.mr.L;
+    const int64_t R = (int64_t)P.rays.n_cams * P.rays.H * P.rays.W;
+    const int64_t HW = (int64_t)P.rays.H * P.rays.W;
+    const int32_t* __restrict__ counts = P.idx.counts;
+    const int32_t* __restrict__ offsets = P.idx.offsets;
+    const int32_t* __restrict__ ids = P.idx.ids;
+    const float* __restrict__ rec = P.rec;
+    const float* __restrict__ lgp = P.lgp;
+
+    const float gD = (rl.valid && P.g_depth) ? P.g_depth[rl.ray] : 0.0f;
+    float gS[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+        gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[((int64_t)rl.cam * P.C + c) * HW + rl.pix] : 0.0f;
+
+    int64_t st[6] = {0, 0, 0, 0, 0, 0};
+    const int nck = (L + KC - 1) / KC;
+    float Q = 0.0f;
+    for (int ci = nck - 1; ci >= 0; --ci) {
+        const float Tc = rl.valid ? P.ckpt[(int64_t)ci * R + rl.ray] : 0.0f;
+        if (wave_ballot(Tc > 0.0f) == 0) continue;
+        const int j0 = ci * KC;
+
+        // ---- chunk geometry + bitmap of the listed ids ----------------------
+        for (int w = lane; w < nw; w += 64) bm[w] = 0u;
+        wave_lds_sync();
+        float sx[KC], sy[KC], sz[KC];
+        int pv[KC];
+        int last_v = -1;
+#pragma unroll
+        for (int jj = 0; jj < KC; ++jj) {
+            pv[jj] = -1;
+            sx[jj] = sy[jj] = sz[jj] = 0.0f;
+            if (j0 + jj < L) {
+                const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
+                                                   rl.dx, rl.dy, rl.dz);
+                sx[jj] = sp.x; sy[jj] = sp.y; sz[jj] = sp.z;
+                int n = 0, f = 0;
+                bool act = (Tc > 0.0f) && (sp.v >= 0);
+                if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+                if (act) pv[jj] = pack_voxel(sp.ix, sp.iy, sp.iz);
+                bool pend = act;
+                uint64_t m;
+                while ((m = wave_ballot(pend)) != 0) {
+                    const int leader = __builtin_ctzll(m);
+                    const int v0 = readlane_i(sp.v, leader);
+                    const int f0 = readlane_i(f, leader);
+                    int n0 = readlane_i(n, leader);
+                    if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity)
+                        n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                    if (v0 != last_v) {
+                        for (int e = lane; e < n0; e += 64) {
+                            const int k = ids[f0 + e];
+                            if ((unsigned)k < (unsigned)P.N) atomicOr(&bm[k >> 5], 1u << (k & 31));
+                        }
+                        last_v = v0;
+                    }
+                    pend = pend && (sp.v != v0);
+                }
+            }
+        }
+        wave_lds_sync();
+
+        // ---- pass 1: a_j and G_j over the union, ascending id ---------------
+        float a[KC], G[KC];
+#pragma unroll
+        for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
+        for_each_marked(bm, nw, lane, [&](int k) {
+            const float* r = rec + (size_t)k * REC;
+            const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+            bool mem[KC];
+            bool anym = false;
+#pragma unroll
+            for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
+            if (wave_ballot(anym) == 0) return;
+            const float* lg = lgp + (size_t)k * CP;
+            float gam = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+            const float sig = r[15];
+#pragma unroll
+            for (int jj = 0; jj < KC; ++jj) {
+                if (mem[jj]) {
+                    if (STATS) { st[1] += 1; if (pair_kept(r, sx[jj], sy[jj], sz[jj])) st[2] += 1; }
+                    const float p = eval_p(r, sx[jj], sy[jj], sz[jj]);
+                    if (p != 0.0f) {
+                        a[jj] = fmaf(p, sig, a[jj]);
+                        G[jj] = fmaf(p, gam, G[jj]);
+                    }
+                }
+            }
+        });
+
+        // ---- compositing and its adjoint (per lane) -------------------------
+        float Tj[KC];
+        {
+            float T = Tc;
+#pragma unroll
+            for (int jj = 0; jj < KC; ++jj) {
+                Tj[jj] = T;
+                T = T * (1.0f - fminf(a[jj], 1.0f));
+            }
+        }
+#pragma unroll
+        for (int jj = KC - 1; jj >= 0; --jj) {
+            if (j0 + jj < L) {
+                const float t = P.mr.t_near + (float)(j0 + jj) * P.mr.delta;
+                const float al = fminf(a[jj], 1.0f);
+                const float Gf = fmaf(gD, t, G[jj]);
+                const float dal = Tj[jj] * (Gf - Q);
+                Q = fmaf(al, Gf, (1.0f - al) * Q);
+                const float da = (a[jj] < 1.0f) ? dal : 0.0f;
+                const float w = Tj[jj] * al;
+                if (STATS && pv[jj] >= 0) st[0] += 1;
+                if (!(Tj[jj] > 0.0f) || (da == 0.0f && w == 0.0f)) pv[jj] = -1;
+                if (STATS && pv[jj] >= 0) st[3] += 1;
+                a[jj] = da;     // reuse: dL/da_j
+                G[jj] = w;      // reuse: w_j
+            }
+        }
+
+        // ---- pass 2: per-primitive adjoint over the union -------------------
+        for_each_marked(bm, nw, lane, [&](int k) {
+            const float* r = rec + (size_t)k * REC;
+            const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+            bool mem[KC];
+            bool anym = false;
+#pragma unroll
+            for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
+            if (wave_ballot(anym) == 0) return;
+            const float* lg = lgp + (size_t)k * CP;
+            float gam = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+            const float a_ = r[12], b_ = r[13], e_ = r[14], sig = r[15];
+            float x[VP];
+#pragma unroll
+            for (int i = 0; i < VP; ++i) x[i] = 0.0f;
+            float om = 0.0f;          // sum_j w_j p_jk
+            bool contrib = false;
+#pragma unroll
+            for (int jj = 0; jj < KC; ++jj) {
+                if (mem[jj]) {
+                    PairEval ev;
+                    float dd[3];
+                    const bool kept = eval_pair(r, sx[jj], sy[jj], sz[jj], dd, ev);
+                    if (STATS) { st[4] += 1; if (kept) st[5] += 1; }
+                    if (kept && ev.p > 0.0f) {
+                        contrib = true;
+                        const float da = a[jj], w = G[jj];
+                        const float dp = fmaf(da, sig, w * gam);
+                        const float df = -ev.p * dp;
+                        const float invA = ev.A > 0.0f ? hw_rcp(ev.A) : 0.0f;
+                        const float cu = df * e_ * a_ * ev.B * invA;
+                        const float gu = ev.u != 0.0f ? cu * ev.X * hw_rcp(ev.u) : 0.0f;
+                        const float gv = ev.v != 0.0f ? cu * ev.Y * hw_rcp(ev.v) : 0.0f;
+                        const float gw = ev.w != 0.0f ? df * b_ * ev.Z * hw_rcp(ev.w) : 0.0f;
+                        const float gx0 = gu * r[17], gx1 = gv * r[18], gx2 = gw * r[19];
+                        const float lnA = ev.A > 0.0f ? ev.lA * LN2 : 0.0f;
+                        const float XlU = ev.X > 0.0f ? ev.X * ev.lu * LN2 : 0.0f;
+                        const float YlV = ev.Y > 0.0f ? ev.Y * ev.lv * LN2 : 0.0f;
+                        const float ZlW = ev.Z > 0.0f ? ev.Z * ev.lw * LN2 : 0.0f;
+                        const float dfde1 = -0.5f * e_ * b_ * ev.B * lnA - 0.5f * b_ * b_ * ZlW;
+                        const float dfde2 = 0.5f * e_ * a_ * ev.B * (lnA - a_ * (XlU + YlV) * invA);
+                        x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
+                        x[A_E1] = fmaf(df, dfde1, x[A_E1]);
+                        x[A_E2] = fmaf(df, dfde2, x[A_E2]);
+                        x[A_XS + 0] += gx0; x[A_XS + 1] += gx1; x[A_XS + 2] += gx2;
+                        x[A_R + 0] = fmaf(gx0, dd[0], x[A_R + 0]);
+                        x[A_R + 1] = fmaf(gx0, dd[1], x[A_R + 1]);
+                        x[A_R + 2] = fmaf(gx0, dd[2], x[A_R + 2]);
+                        x[A_R + 3] = fmaf(gx1, dd[0], x[A_R + 3]);
+                        x[A_R + 4] = fmaf(gx1, dd[1], x[A_R + 4]);
+                        x[A_R + 5] = fmaf(gx1, dd[2], x[A_R + 5]);
+                        x[A_R + 6] = fmaf(gx2, dd[0], x[A_R + 6]);
+                        x[A_R + 7] = fmaf(gx2, dd[1], x[A_R + 7]);
+                        x[A_R + 8] = fmaf(gx2, dd[2], x[A_R + 8]);
+                        om = fmaf(w, ev.p, om);
+                    }
+                }
+            }
+            if (wave_ballot(contrib) == 0) return;
+#pragma unroll
+            for (int c = 0; c < CP; ++c) x[A_LG + c] = om * gS[c];
+            const float tot = transpose_reduce<VP>(x, lane);
+            constexpr int shift = 6 - Log2<VP>::v;
+            const int vi = lane >> shift;
+            if (((lane & ((1 << shift) - 1)) == 0) && vi < V && (vi < A_LG || vi - A_LG < P.C))
+                atomicAdd(P.acc + (size_t)k * VP + vi, tot);
+        });
+    }
+    if (STATS && rl.valid)
+        for (int i = 0; i < 6; ++i) atomicAdd((unsigned long long*)&P.stats[i], (unsigned long long)st[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -534,8 +783,9 @@ static TileMap make_tiles(const RaysDev& rays, const TuneDev& tune) {
 }
 
 template <int CP>
-static void prep(const PrimsDev& pr, const WsLayout& l, hipStream_t st) {
-    if (pr.n > 0) hipLaunchKernelGGL(k_prep_records<CP>, dim3((pr.n + 255) / 256), dim3(256), 0, st, pr, l.rec, l.lgp);
+static void prep(const PrimsDev& pr, const GridDev& g, const WsLayout& l, hipStream_t st) {
+    if (pr.n > 0)
+        hipLaunchKernelGGL(k_prep_records<CP>, dim3((pr.n + 255) / 256), dim3(256), 0, st, pr, g, l.rec, l.lgp);
 }
 
 template <int CP>
@@ -559,26 +809,52 @@ hipError_t launch_render_fwd(const GridDev& g, const IndexDev& idx, const PrimsD
     const int wpb = tune.waves_per_block;
     const dim3 grid((P.tm.n_tiles + wpb - 1) / wpb), block(64 * wpb);
     switch (CP) {
-        case 4: prep<4>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<4>(P, grid, block, st); break;
-        case 8: prep<8>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<8>(P, grid, block, st); break;
-        case 17: prep<17>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<17>(P, grid, block, st); break;
-        default: prep<32>(pr, l, st); if (P.tm.n_tiles) fwd_dispatch<32>(P, grid, block, st); break;
+        case 4: prep<4>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<4>(P, grid, block, st); break;
+        case 8: prep<8>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<8>(P, grid, block, st); break;
+        case 17: prep<17>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<17>(P, grid, block, st); break;
+        default: prep<32>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<32>(P, grid, block, st); break;
     }
     return hipGetLastError();
 }
 
+static int bitmap_words(int n) { return ((n + 31) / 32 + 63) / 64 * 64; }
+
+// The primitive-major backward needs the chunk in registers (K <= 8), a
+// per-wave bitmap that fits the LDS budget, and voxel coordinates that fit the
+// packed form.  Otherwise the sample-major backward runs.
+bool bwd_primitive_major_ok(const GridDev& g, int n, int K, int wpb) {
+    if (!(K == 4 || K == 8)) return false;
+    if (g.X > KM_MAX_XY || g.Y > KM_MAX_XY || g.Z > KM_MAX_Z) return false;
+    return (size_t)wpb * bitmap_words(n) * sizeof(uint32_t) <= 64 * 1024;
+}
+
 template <int CP>
-static void bwd_run(const BwdParams& P, const PrimsDev& pr, const WsLayout& l, int wpb, float* g_means,
+static void bwd_run(const BwdParams& P, const PrimsDev& pr, const WsLayout& l, int wpb, int bwd_mode, float* g_means,
                     float* g_quats, float* g_scales, float* g_eps, float* g_opacity, float* g_logits,
                     hipStream_t st) {
-    prep<CP>(pr, l, st);
+    prep<CP>(pr, P.g, l, st);
     const int64_t nacc = (int64_t)pr.n * AccRow<CP>::P;
     if (nacc > 0) hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((nacc + 255) / 256, 4096)), dim3(256), 0, st,
                                      l.acc, nacc, 0.0f);
     if (P.tm.n_tiles) {
         const dim3 grid((P.tm.n_tiles + wpb - 1) / wpb), block(64 * wpb);
-        const size_t shm = (size_t)wpb * 4 * P.mr.K * 64 * sizeof(float);
-        hipLaunchKernelGGL(k_render_bwd<CP>, grid, block, shm, st, P);
+        const bool km = bwd_mode != 1 && bwd_primitive_major_ok(P.g, P.N, P.mr.K, wpb);
+        if (km) {
+            BwdParams Q = P;
+            Q.bitmap_words = bitmap_words(pr.n);
+            const size_t shm = (size_t)wpb * Q.bitmap_words * sizeof(uint32_t);
+            if (P.mr.K == 4) {
+                if (P.stats) hipLaunchKernelGGL((k_render_bwd_km<CP, 4, true>), grid, block, shm, st, Q);
+                else hipLaunchKernelGGL((k_render_bwd_km<CP, 4, false>), grid, block, shm, st, Q);
+            } else {
+                if (P.stats) hipLaunchKernelGGL((k_render_bwd_km<CP, 8, true>), grid, block, shm, st, Q);
+                else hipLaunchKernelGGL((k_render_bwd_km<CP, 8, false>), grid, block, shm, st, Q);
+            }
+        } else {
+            const size_t shm = (size_t)wpb * 4 * P.mr.K * 64 * sizeof(float);
+            if (P.stats) hipLaunchKernelGGL((k_render_bwd<CP, true>), grid, block, shm, st, P);
+            else hipLaunchKernelGGL((k_render_bwd<CP, false>), grid, block, shm, st, P);
+        }
     }
     if (pr.n > 0)
         hipLaunchKernelGGL(k_finalize<CP>, dim3((pr.n + 255) / 256), dim3(256), 0, st, pr, (const float*)l.acc,
@@ -588,19 +864,20 @@ static void bwd_run(const BwdParams& P, const PrimsDev& pr, const WsLayout& l, i
 hipError_t launch_render_bwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
                              const MarchDev& mr, const float* ckpt, const float* g_depth, const float* g_sem,
                              float* g_means, float* g_quats, float* g_scales, float* g_eps, float* g_opacity,
-                             float* g_logits, const TuneDev& tune, void* ws, hipStream_t st) {
+                             float* g_logits, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st) {
     const int CP = padded_classes(pr.C);
     const WsLayout l = carve(ws, pr.n, pr.C);
     BwdParams P;
+    P.stats = stats;
     P.g = g; P.idx = idx; P.N = pr.n; P.C = pr.C; P.rec = l.rec; P.lgp = l.lgp; P.rays = rays; P.mr = mr;
     P.tm = make_tiles(rays, tune);
     P.ckpt = ckpt; P.g_depth = g_depth; P.g_sem = g_sem; P.acc = l.acc;
     const int wpb = tune.waves_per_block;
     switch (CP) {
-        case 4: bwd_run<4>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
-        case 8: bwd_run<8>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
-        case 17: bwd_run<17>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
-        default: bwd_run<32>(P, pr, l, wpb, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+        case 4: bwd_run<4>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+        case 8: bwd_run<8>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+        case 17: bwd_run<17>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+        default: bwd_run<32>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
     }
     return hipGetLastError();
 }

@@ -20,8 +20,12 @@ namespace sqr {
 //   [15]     sigma
 //   [16]     r_cull: max(|u|,|v|,|w|) >= r_cull  =>  f >= F_CULL
 //   [17..19] 1/s
+//   [20..22] clipped neighbourhood box per axis, int bits lo | hi << 16
+//            (the primitive is listed in voxel v iff v lies in this box)
+//   [23]     unused
 // ---------------------------------------------------------------------------
-constexpr int REC = 20;
+constexpr int REC = 24;
+constexpr int EMPTY_BOX = 0x7fff7fff;
 constexpr float F_CULL = 110.0f;          // exp(-110) = 1.7e-48: 0 in float32
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;
@@ -45,6 +49,7 @@ struct GridDev {
 struct SamplePos {
     float t, x, y, z;
     int v;              // linear voxel id, or -1 outside the grid
+    int ix, iy, iz;     // voxel coordinates (valid when v >= 0)
 };
 
 __device__ __forceinline__ SamplePos pinned_sample(const GridDev& g, float t_near, float delta, int j,
@@ -62,11 +67,15 @@ __device__ __forceinline__ SamplePos pinned_sample(const GridDev& g, float t_nea
     const bool in = (qx >= 0.0f) & (qx < (float)g.X) & (qy >= 0.0f) & (qy < (float)g.Y) &
                     (qz >= 0.0f) & (qz < (float)g.Z);
     // q >= 0 here, so truncation is floor
-    s.v = in ? (((int)qx * g.Y + (int)qy) * g.Z + (int)qz) : -1;
+    s.ix = in ? (int)qx : 0;
+    s.iy = in ? (int)qy : 0;
+    s.iz = in ? (int)qz : 0;
+    s.v = in ? ((s.ix * g.Y + s.iy) * g.Z + s.iz) : -1;
     return s;
 }
 
 // Centre voxel of a primitive along one axis, bounded before conversion.
+// (The same op sequence as the index build, so boxes agree bit for bit.)
 __device__ __forceinline__ int pinned_centre_axis(float m, float lo, float inv, float bound) {
 #pragma clang fp contract(off)
     float q = (m - lo) * inv;
@@ -110,6 +119,15 @@ __device__ __forceinline__ bool eval_pair(const float* __restrict__ rec, float x
     return true;
 }
 
+// Cull test alone (used by the counting variants of the kernels).
+__device__ __forceinline__ bool pair_kept(const float* __restrict__ rec, float x, float y, float z) {
+    const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
+    const float u = fmaf(rec[3], dx, fmaf(rec[4], dy, rec[5] * dz));
+    const float v = fmaf(rec[6], dx, fmaf(rec[7], dy, rec[8] * dz));
+    const float w = fmaf(rec[9], dx, fmaf(rec[10], dy, rec[11] * dz));
+    return fmaxf(fmaxf(fabsf(u), fabsf(v)), fabsf(w)) < rec[16];
+}
+
 // Forward-only evaluation: returns p (0 when culled).
 __device__ __forceinline__ float eval_p(const float* __restrict__ rec, float x, float y, float z) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
@@ -137,6 +155,72 @@ __device__ __forceinline__ uint64_t wave_ballot(bool b) { return __builtin_amdgc
 __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 __device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// Order the LDS accesses of one wavefront (LDS is private to the wave here).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+constexpr int DPP_ROW_MIRROR = 0x140;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_QUAD_SWAP2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int DPP_QUAD_SWAP1 = 0xB1;   // quad_perm [1,0,3,2]
+
+// Sum VP (32 or 64) values over the 64 lanes of a wavefront with a
+// transposing butterfly: at each level a lane keeps half of its values and
+// adds its partner's partial sums of that half.  Levels use
+// v_permlane32_swap, v_permlane16_swap, DPP row_mirror, row_half_mirror and
+// two quad permutes, so no LDS is touched.  On return lane l holds the total
+// of value index l >> (6 - log2 VP).  All 64 lanes must be active.
+template <int VP>
+__device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
+    static_assert(VP == 32 || VP == 64, "VP must be 32 or 64");
+    constexpr int h1 = VP / 2, h2 = h1 / 2, h3 = h2 / 2, h4 = h3 / 2, h5 = h4 / 2;
+#pragma unroll
+    for (int i = 0; i < h1; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[h1 + i]),
+                                                        false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < h2; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[h2 + i]),
+                                                        false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+#pragma unroll
+    for (int i = 0; i < h3; ++i) {
+        const float lo = x[i] + dpp_f<DPP_ROW_MIRROR>(x[i]);
+        const float hi = x[h3 + i] + dpp_f<DPP_ROW_MIRROR>(x[h3 + i]);
+        x[i] = b3 ? hi : lo;
+    }
+#pragma unroll
+    for (int i = 0; i < h4; ++i) {
+        const float lo = x[i] + dpp_f<DPP_ROW_HALF_MIRROR>(x[i]);
+        const float hi = x[h4 + i] + dpp_f<DPP_ROW_HALF_MIRROR>(x[h4 + i]);
+        x[i] = b2 ? hi : lo;
+    }
+#pragma unroll
+    for (int i = 0; i < h5; ++i) {
+        const float lo = x[i] + dpp_f<DPP_QUAD_SWAP2>(x[i]);
+        const float hi = x[h5 + i] + dpp_f<DPP_QUAD_SWAP2>(x[h5 + i]);
+        x[i] = b1 ? hi : lo;
+    }
+    if constexpr (VP == 64) {
+        const float lo = x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
+        const float hi = x[1] + dpp_f<DPP_QUAD_SWAP1>(x[1]);
+        return b0 ? hi : lo;
+    } else {
+        return x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
+    }
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
 // works on one contiguous range of logical blocks (neighbouring ray tiles share
 // voxel lists and primitive records in that XCD's L2).
@@ -144,6 +228,31 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     const int per = nb >> 3, rem = nb & 7;
     const int xcd = b & 7, local = b >> 3;
     return (xcd < rem) ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Clipped box of a primitive, packed lo | hi << 16 per axis.  An empty box is
+// stored as lo = hi = 0x7fff on every axis: no voxel index reaches 0x7fff
+// (dims <= 32767), so every containment / overlap test fails.
+__device__ __forceinline__ void prim_box(const GridDev& g, float mx, float my, float mz, int out[3]) {
+    const int dims[3] = {g.X, g.Y, g.Z};
+    const float lo[3] = {g.lox, g.loy, g.loz};
+    const float m[3] = {mx, my, mz};
+    const float bound = (float)(max(max(g.X, g.Y), g.Z) + g.nv + 2);
+    bool empty = false;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int c = pinned_centre_axis(m[ax], lo[ax], g.inv, bound);
+        const int blo = max(c - g.nv, 0);
+        const int bhi = min(c + g.nv, dims[ax] - 1);
+        if (blo > bhi) empty = true;
+        out[ax] = (blo & 0xffff) | (bhi << 16);
+    }
+    if (empty) out[0] = out[1] = out[2] = EMPTY_BOX;
+}
+
+// lo <= i <= hi for a packed axis range (one subtract, one unsigned compare)
+__device__ __forceinline__ bool in_range(int i, int packed) {
+    const int lo = packed & 0xffff, hi = packed >> 16;
+    return (unsigned)(i - lo) <= (unsigned)(hi - lo);
 }
 
 }  // namespace sqr

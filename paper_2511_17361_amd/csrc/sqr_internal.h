@@ -38,6 +38,7 @@ struct IndexDev {
 struct TuneDev {
     int tile_w;           // 4, 8 or 16 (tile is tile_w x 64/tile_w pixels)
     int waves_per_block;  // 1..4
+    int bwd_mode;         // 0 auto, 1 sample-major, 2 primitive-major
 };
 
 // class count padded to the compiled widths
@@ -47,9 +48,11 @@ size_t render_workspace_bytes(int n, int C);
 hipError_t launch_render_fwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
                              const MarchDev& mr, float* depth, float* sem, float* probs, float* t_final,
                              float* ckpt, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
+// whether the primitive-major backward applies to these arguments
+bool bwd_primitive_major_ok(const GridDev& g, int n, int K, int wpb);
 hipError_t launch_render_bwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
                              const MarchDev& mr, const float* ckpt, const float* g_depth, const float* g_sem,
                              float* g_means, float* g_quats, float* g_scales, float* g_eps, float* g_opacity,
-                             float* g_logits, const TuneDev& tune, void* ws, hipStream_t st);
+                             float* g_logits, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
 
 }  // namespace sqr

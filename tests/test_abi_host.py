@@ -106,13 +106,14 @@ def _index():
     (lambda a: setattr(a["index"], "counts", None), L.SQ_ERR_INVALID),
     (lambda a: a.__setitem__("ws_bytes", 16), L.SQ_ERR_CAPACITY),
     (lambda a: a.__setitem__("tile_w", 5), L.SQ_ERR_INVALID),
+    (lambda a: a.__setitem__("tile_w", 0), L.SQ_ERR_INVALID),
 ])
 def test_render_fwd_rejects_bad_arguments_without_launch(mutate, code):
     lib = L.load()
     args = dict(grid=_grid(), prims=_prims(), rays=_rays(), march=_march(), index=_index(), ws_bytes=1 << 30,
                 tile_w=8)
     mutate(args)
-    t = L.SqTuning(args["tile_w"], 4)
+    t = L.SqTuning(args["tile_w"], 4, 0)
     rc = lib.sq_render_fwd(ct.byref(args["grid"]), ct.byref(args["index"]), ct.byref(args["prims"]),
                            ct.byref(args["rays"]), ct.byref(args["march"]), FAKE, FAKE, None, FAKE, None, None,
                            ct.byref(t), 0x100000, args["ws_bytes"], None)
@@ -127,11 +128,11 @@ def test_render_bwd_needs_supported_chunk():
     for K in (0, 3, 32):
         m = _march(K=K)
         rc = lib.sq_render_bwd(ct.byref(g), ct.byref(i), ct.byref(p), ct.byref(r), ct.byref(m), FAKE, FAKE, FAKE,
-                               ct.byref(gr), None, 0x100000, 1 << 30, None)
+                               ct.byref(gr), None, None, 0x100000, 1 << 30, None)
         assert rc == L.SQ_ERR_INVALID
     m = _march(K=8)
     rc = lib.sq_render_bwd(ct.byref(g), ct.byref(i), ct.byref(p), ct.byref(r), ct.byref(m), None, FAKE, FAKE,
-                           ct.byref(gr), None, 0x100000, 1 << 30, None)
+                           ct.byref(gr), None, None, 0x100000, 1 << 30, None)
     assert rc == L.SQ_ERR_INVALID and "ckpt" in lib.sq_last_error().decode()
 
 

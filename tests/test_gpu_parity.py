@@ -169,17 +169,25 @@ def test_fwd_deterministic_and_ckpt_consistent():
 # backward
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("K", [4, 8, 16])
-@pytest.mark.parametrize("seed,n,C,opac", [(40, 6, 3, 0.4), (41, 12, 4, 1.0), (42, 20, 17, 0.8), (43, 8, 32, 0.6)])
-def test_bwd_small_scenes(seed, n, C, opac, K):
-    _say("bwd small", seed, n, C, opac, K)
+@pytest.mark.parametrize("K,mode", [(4, 1), (4, 2), (8, 1), (8, 2), (16, 1), (16, 0)])
+@pytest.mark.parametrize("seed,n,C,opac", [(40, 6, 3, 0.4), (41, 12, 4, 1.0), (42, 20, 17, 0.8), (43, 8, 32, 0.6),
+                                           (44, 60, 8, 0.9)])
+def test_bwd_small_scenes(seed, n, C, opac, K, mode):
+    _say("bwd small", seed, n, C, opac, K, mode)
     sc = random_scene(seed, n=n, n_classes=C, width=19, height=13, n_samples=37, opacity_hi=opac,
                       dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0)
     rng = np.random.default_rng(seed)
     g_d, g_s = synth.upstream_grads(rng, sc.rays, C)
-    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=K)
+    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=K, tuning=api.Tuning(8, 4, mode))
     ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
-    H.assert_grads_close(g, ref, f"seed{seed} K{K}")
+    H.assert_grads_close(g, ref, f"seed{seed} K{K} mode{mode}")
+
+
+def test_bwd_forcing_primitive_major_where_it_does_not_apply_is_rejected():
+    sc = random_scene(45, n=5, width=9, height=7)
+    with pytest.raises(Exception, match="status -4"):
+        H.run_fwd_bwd(sc, *synth.upstream_grads(np.random.default_rng(0), sc.rays, 3), ckpt_every=16,
+                      tuning=api.Tuning(8, 4, 2))
 
 
 def test_bwd_config0():
@@ -192,7 +200,8 @@ def test_bwd_config0():
     H.assert_grads_close(g, ref, "cfg0")
 
 
-def test_bwd_config2_sparse_upstream():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_bwd_config2_sparse_upstream(mode):
     """Config 2 (config 1 shapes): upstream gradients non-zero on 1500 rays only,
     so the oracle's gradient is exact while touching those rays alone."""
     sc = synth.config(2)
@@ -206,7 +215,7 @@ def test_bwd_config2_sparse_upstream():
     cams, Hh, Ww = sc.rays.shape
     g_d_img = g_d.reshape(cams, Hh, Ww)
     g_s_img = g_s.reshape(cams, Hh, Ww, C).transpose(0, 3, 1, 2).copy()
-    _say("bwd config2")
-    _, g = H.run_fwd_bwd(sc, g_d_img, g_s_img)
+    _say("bwd config2", mode)
+    _, g = H.run_fwd_bwd(sc, g_d_img, g_s_img, tuning=api.Tuning(8, 4, mode))
     ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d[ids], g_s[ids], ray_ids=ids)
     H.assert_grads_close(g, ref, "cfg2")
