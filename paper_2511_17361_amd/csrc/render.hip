@@ -38,6 +38,10 @@ int padded_classes(int C) {
 }
 static int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
 
+// Occupancy targets (waves per SIMD) that the register allocator must meet.
+#define FWD_WPE(CP) ((CP) <= 8 ? 6 : (CP) <= 17 ? 5 : 3)
+#define BWD_WPE(CP, KC) ((KC) == 4 && (CP) <= 17 ? 4 : 3)
+
 // ---------------------------------------------------------------------------
 // Per-primitive preparation
 // ---------------------------------------------------------------------------
@@ -133,15 +137,15 @@ struct FwdParams {
 // Forward
 // ---------------------------------------------------------------------------
 template <int CP, bool CKPT, bool STATS>
-__global__ __launch_bounds__(256) void k_render_fwd(FwdParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP), 8))) void k_render_fwd(FwdParams P) {
     RayLane rl;
     if (!map_tile(P.tm, P.rays, rl)) return;    // whole wavefront
     const int64_t R = (int64_t)P.rays.n_cams * P.rays.H * P.rays.W;
     const int32_t* __restrict__ counts = P.idx.counts;
     const int32_t* __restrict__ offsets = P.idx.offsets;
-    const int32_t* __restrict__ ids = P.idx.ids;
-    const float* __restrict__ rec = P.rec;
-    const float* __restrict__ lgp = P.lgp;
+    const ci_ptr ids = as_const(P.idx.ids);
+    const cf_ptr rec = as_const(P.rec);
+    const cf_ptr lgp = as_const(P.lgp);
     const int L = P.mr.L, K = P.mr.K;
 
     float T = rl.valid ? 1.0f : 0.0f;
@@ -186,12 +190,12 @@ __global__ __launch_bounds__(256) void k_render_fwd(FwdParams P) {
                     for (int e = 0; e < n0; ++e) {
                         const int k = ids[f0 + e];
                         if ((unsigned)k >= (unsigned)P.N) continue;
-                        const float* r = rec + (size_t)k * REC;
+                        const cf_ptr r = rec + (size_t)k * REC;
                         const float p = eval_p(r, cur.x, cur.y, cur.z);
                         if (STATS && pair_kept(r, cur.x, cur.y, cur.z)) ++st_nz;
                         if (p != 0.0f) {
                             a = fmaf(p, r[15], a);
-                            const float* lg = lgp + (size_t)k * CP;
+                            const cf_ptr lg = lgp + (size_t)k * CP;
 #pragma unroll
                             for (int c = 0; c < CP; ++c) s[c] = fmaf(p, lg[c], s[c]);
                         }
@@ -291,9 +295,9 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
     const int64_t HW = (int64_t)P.rays.H * P.rays.W;
     const int32_t* __restrict__ counts = P.idx.counts;
     const int32_t* __restrict__ offsets = P.idx.offsets;
-    const int32_t* __restrict__ ids = P.idx.ids;
-    const float* __restrict__ rec = P.rec;
-    const float* __restrict__ lgp = P.lgp;
+    const ci_ptr ids = as_const(P.idx.ids);
+    const cf_ptr rec = as_const(P.rec);
+    const cf_ptr lgp = as_const(P.lgp);
 
     const float gD = (rl.valid && P.g_depth) ? P.g_depth[rl.ray] : 0.0f;
     float gS[CP];
@@ -333,12 +337,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                     for (int e = 0; e < n0; ++e) {
                         const int k = ids[f0 + e];
                         if ((unsigned)k >= (unsigned)P.N) continue;
-                        const float* r = rec + (size_t)k * REC;
+                        const cf_ptr r = rec + (size_t)k * REC;
                         const float p = eval_p(r, sp.x, sp.y, sp.z);
                         if (STATS && pair_kept(r, sp.x, sp.y, sp.z)) st[2] += 1;
                         if (p != 0.0f) {
                             a = fmaf(p, r[15], a);
-                            const float* lg = lgp + (size_t)k * CP;
+                            const cf_ptr lg = lgp + (size_t)k * CP;
                             float gam = 0.0f;
 #pragma unroll
                             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
@@ -386,8 +390,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                 for (int e = 0; e < n0; ++e) {
                     const int k = ids[f0 + e];
                     if ((unsigned)k >= (unsigned)P.N) continue;
-                    const float* r = rec + (size_t)k * REC;
-                    const float* lg = lgp + (size_t)k * CP;
+                    const cf_ptr r = rec + (size_t)k * REC;
+                    const cf_ptr lg = lgp + (size_t)k * CP;
                     float x[VP];
 #pragma unroll
                     for (int i = 0; i < VP; ++i) x[i] = 0.0f;
@@ -500,7 +504,7 @@ __device__ __forceinline__ void for_each_marked(const uint32_t* bm, int nw, int 
 }
 
 template <int CP, int KC, bool STATS>
-__global__ __launch_bounds__(256) void k_render_bwd_km(BwdParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP, KC), 8))) void k_render_bwd_km(BwdParams P) {
     extern __shared__ uint32_t bm_all[];
     RayLane rl;
     if (!map_tile(P.tm, P.rays, rl)) return;
@@ -514,9 +518,9 @@ __global__ __launch_bounds__(256) void k_render_bwd_km(BwdParams P) {
     const int64_t HW = (int64_t)P.rays.H * P.rays.W;
     const int32_t* __restrict__ counts = P.idx.counts;
     const int32_t* __restrict__ offsets = P.idx.offsets;
-    const int32_t* __restrict__ ids = P.idx.ids;
-    const float* __restrict__ rec = P.rec;
-    const float* __restrict__ lgp = P.lgp;
+    const ci_ptr ids = as_const(P.idx.ids);
+    const cf_ptr rec = as_const(P.rec);
+    const cf_ptr lgp = as_const(P.lgp);
 
     const float gD = (rl.valid && P.g_depth) ? P.g_depth[rl.ray] : 0.0f;
     float gS[CP];
@@ -577,14 +581,14 @@ __global__ __launch_bounds__(256) void k_render_bwd_km(BwdParams P) {
 #pragma unroll
         for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
         for_each_marked(bm, nw, lane, [&](int k) {
-            const float* r = rec + (size_t)k * REC;
+            const cf_ptr r = rec + (size_t)k * REC;
             const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            const float* lg = lgp + (size_t)k * CP;
+            const cf_ptr lg = lgp + (size_t)k * CP;
             float gam = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
@@ -632,14 +636,14 @@ __global__ __launch_bounds__(256) void k_render_bwd_km(BwdParams P) {
 
         // ---- pass 2: per-primitive adjoint over the union -------------------
         for_each_marked(bm, nw, lane, [&](int k) {
-            const float* r = rec + (size_t)k * REC;
+            const cf_ptr r = rec + (size_t)k * REC;
             const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            const float* lg = lgp + (size_t)k * CP;
+            const cf_ptr lg = lgp + (size_t)k * CP;
             float gam = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);

@@ -30,6 +30,15 @@ constexpr float F_CULL = 110.0f;          // exp(-110) = 1.7e-48: 0 in float32
 constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;
 
+// Read-only views in the constant address space.  The kernels store floats
+// (checkpoints, atomics) while they read records and logits; through these
+// pointers the compiler knows the reads are invariant and keeps wave-uniform
+// ones on the scalar path (s_load into SGPRs) instead of vector loads.
+typedef const __attribute__((address_space(4))) float* cf_ptr;
+typedef const __attribute__((address_space(4))) int* ci_ptr;
+__device__ __forceinline__ cf_ptr as_const(const float* p) { return (cf_ptr)p; }
+__device__ __forceinline__ ci_ptr as_const(const int* p) { return (ci_ptr)p; }
+
 // Hardware base-2 transcendentals (v_log_f32 / v_exp_f32).
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -94,7 +103,7 @@ struct PairEval {
 };
 
 // Returns false when the pair is culled (float32 exp(-f) would be exactly 0).
-__device__ __forceinline__ bool eval_pair(const float* __restrict__ rec, float x, float y, float z,
+__device__ __forceinline__ bool eval_pair(cf_ptr rec, float x, float y, float z,
                                           float dxyz[3], PairEval& e) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
     dxyz[0] = dx; dxyz[1] = dy; dxyz[2] = dz;
@@ -120,7 +129,7 @@ __device__ __forceinline__ bool eval_pair(const float* __restrict__ rec, float x
 }
 
 // Cull test alone (used by the counting variants of the kernels).
-__device__ __forceinline__ bool pair_kept(const float* __restrict__ rec, float x, float y, float z) {
+__device__ __forceinline__ bool pair_kept(cf_ptr rec, float x, float y, float z) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
     const float u = fmaf(rec[3], dx, fmaf(rec[4], dy, rec[5] * dz));
     const float v = fmaf(rec[6], dx, fmaf(rec[7], dy, rec[8] * dz));
@@ -129,7 +138,7 @@ __device__ __forceinline__ bool pair_kept(const float* __restrict__ rec, float x
 }
 
 // Forward-only evaluation: returns p (0 when culled).
-__device__ __forceinline__ float eval_p(const float* __restrict__ rec, float x, float y, float z) {
+__device__ __forceinline__ float eval_p(cf_ptr rec, float x, float y, float z) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
     const float u = fmaf(rec[3], dx, fmaf(rec[4], dy, rec[5] * dz));
     const float v = fmaf(rec[6], dx, fmaf(rec[7], dy, rec[8] * dz));
