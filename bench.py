@@ -34,11 +34,19 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Algorithmic FLOPs per unit (each FMA = 2, add/mul/compare = 1, transcendental = 1)
 #   listed pair (transform + cull test):                 3 sub + 9 FMA + 3 abs/max/cmp = 24
 #   evaluated pair, forward:      24 + 9 trans + 5 mul + 2 add + FMA(a) + C FMA(s) = 40 + 2 + 2C
-#   evaluated pair, backward pass 1: 40 + FMA(a) + C FMA(gamma) + FMA(G)          = 44 + 2C
-#   evaluated pair, backward pass 2: 40 + C FMA(gamma) + derivatives (~81)
+#   evaluated pair, backward recompute: 40 + FMA(a) + C FMA(gamma) + FMA(G)     = 44 + 2C
+#   evaluated pair, backward adjoint: 40 + C FMA(gamma) + derivatives (~81)
 #                                    + one add per summed contribution (15 + C)   = 136 + 3C
 #   sample visited (pinned point + voxel): 6 + 6 + 6 compares + 5 int            = 23
 #   live sample compositing: min, 2 mul, FMA(D), C FMA(S), 2 (T)                  = 7 + 2C
+# The backward's algorithmic recompute is the forward's work (its unit counts);
+# evaluations the kernel spends past a ray's saturation inside its last chunk
+# are overhead and are not counted.
+
+
+def api_cp(C):
+    """class count padded to the compiled kernel widths"""
+    return 4 if C <= 4 else 8 if C <= 8 else 17 if C <= 17 else 32
 
 
 def flops_fwd(st, C):
@@ -46,9 +54,27 @@ def flops_fwd(st, C):
     return 24 * listed + (16 + 2 * C) * evaluated + (23 + 7 + 2 * C) * samples
 
 
-def flops_bwd(st, C):
-    return (24 * st["listed1"] + (20 + 2 * C) * st["eval1"] + 24 * st["listed2"] + (112 + 3 * C) * st["eval2"]
-            + (23 + 7 + 2 * C) * st["samples1"] + (23 + 10) * st["samples2"])
+def flops_bwd(fst, bst, C):
+    recompute = 24 * fst["listed"] + (20 + 2 * C) * fst["evaluated"] + (23 + 7 + 2 * C) * fst["samples"]
+    adjoint = 24 * bst["listed2"] + (112 + 3 * C) * bst["eval2"] + (23 + 10) * bst["samples2"]
+    return recompute + adjoint
+
+
+def recorded_traffic(kernel_name):
+    """Calibrated HBM bytes per launch of `kernel_name` from the committed counter
+    runs (profiles/hbm_traffic.json), or None when the kernel sources changed
+    since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = b"".join(open(os.path.join(ROOT, "paper_2511_17361_amd", "csrc", f), "rb").read()
+                   for f in ("render.hip", "sqr_device.h"))
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    k = rec["kernels"].get(kernel_name)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
 def parse():
@@ -57,13 +83,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=4, help="workload config (4 = 6x900x1600, 25.6k SQs)")
-    ap.add_argument("--ckpt-every", type=int, default=8)
+    ap.add_argument("--ckpt-every", type=int, default=4)
     ap.add_argument("--tile-w", type=int, default=8)
     ap.add_argument("--wpb", type=int, default=4)
     ap.add_argument("--bwd-mode", type=int, default=0, help="0 auto, 1 sample-major, 2 primitive-major")
-    ap.add_argument("--cpu-rays", type=int, default=4096, help="rays in the oracle's CPU sample")
+    ap.add_argument("--cpu-rays", type=int, default=8192, help="rays in the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after timing, copy a buffer of this many MiB once (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -204,16 +232,23 @@ def main():
         if bst is not None:
             b = {k: int(v) for k, v in bst.items()}
             result["units_bwd"] = b
-            f_bwd = flops_bwd(b, C)
+            f_bwd = flops_bwd(fst, b, C)
             ach = f_bwd / (t_bwd / 1e3) / 1e12
-            result["roofline"] = {"bound": "alu", "kernel": "k_render_bwd", "achieved": ach,
+            kname = f"sqr::k_render_bwd_km<{api_cp(C)}, {K}, false>"
+            result["roofline"] = {"bound": "alu", "kernel": kname, "achieved": ach,
                                   "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
-                                  "traffic": None}
-        else:
-            ach = result["fwd_tflops"]
-            result["roofline"] = {"bound": "alu", "kernel": "k_render_fwd", "achieved": ach,
-                                  "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
-                                  "traffic": None}
+                                  "traffic": recorded_traffic(kname), "flop_per_launch": f_bwd,
+                                  "kernel_ms": t_bwd}
+        result["fwd_roofline_frac"] = result["fwd_tflops"] / VALU_PEAK_TFLOPS
+
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty(n, device=dev)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = 4 * n
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_rays)
