@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--cpu-rays", type=int, default=8192, help="rays in the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="use --tile-w/--wpb/--bwd-mode instead of autotuning the step")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB once (HBM counter calibration)")
     return ap.parse_args()
@@ -129,68 +131,85 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
-    sc = synth.config(args.config)
-    grid, march = api.Grid.of(sc.grid), api.March.of(sc.march)
-    prims = api.Prims.from_numpy(sc.prims, dev)
-    rays = api.Rays.from_numpy(sc.rays, dev)
-    C = sc.prims.n_classes
-    K = args.ckpt_every
-    tune = api.Tuning(args.tile_w, args.wpb, args.bwd_mode)
+    scenes = [synth.config(3, s) for s in range(8)] if args.config == 3 else [synth.config(args.config)]
+    sc0 = scenes[0]
+    grid = api.Grid.of(sc0.grid)
+    march = api.March(sc0.march.n_samples, sc0.march.t_near, sc0.march.t_far, args.ckpt_every)
+    C = sc0.prims.n_classes
+    dprims = [(api.Prims.from_numpy(s.prims, dev), api.Rays.from_numpy(s.rays, dev)) for s in scenes]
+    batch = api.Batch(grid, march, dprims, device=dev, min_chunk=4)
     rng = np.random.default_rng(1)
-    g_d_np, g_s_np = synth.upstream_grads(rng, sc.rays, C)
-    g_d = torch.from_numpy(g_d_np).to(dev)
-    g_s = torch.from_numpy(g_s_np).to(dev)
-    ws_i, ws_r = api.Workspace(dev), api.Workspace(dev)
-    R = sc.rays.n_rays
-    Ls = sc.march.n_samples
-    stream = torch.cuda.current_stream()
+    for i, s in enumerate(scenes):
+        gd, gs = synth.upstream_grads(rng, s.rays, C)
+        batch.set_upstream(i, torch.from_numpy(gd).to(dev), torch.from_numpy(gs).to(dev))
+    R = batch.n_rays
+    Ls = sc0.march.n_samples
+    stream = torch.cuda.Stream(device=dev)
 
-    idx = api.build_index(grid, prims, ws=ws_i)
-    fwd_out = api.render_fwd(grid, idx, prims, rays, march, ckpt_every=K, tuning=tune, ws=ws_r)
-    bwd_out = api.render_bwd(grid, idx, prims, rays, march, fwd_out["ckpt"], K, g_d, g_s, tuning=tune, ws=ws_r)
+    tune = api.Tuning(args.tile_w, args.wpb, args.bwd_mode, 0, args.ckpt_every)
+    tuned_ms = None
+    if args.autotune:
+        with torch.cuda.stream(stream):
+            tune, tuned_ms = batch.autotune(api.default_candidates(), reps=2, stream=stream)
     torch.cuda.synchronize()
-    E = idx.checked_total()
 
-    def step(ev=None):
-        if ev:
-            ev[0].record(stream)
-        api.build_index(grid, prims, ws=ws_i, out=idx)
-        if ev:
-            ev[1].record(stream)
-        api.render_fwd(grid, idx, prims, rays, march, ckpt_every=K, tuning=tune, ws=ws_r, out=fwd_out)
-        if ev:
-            ev[2].record(stream)
-        api.render_bwd(grid, idx, prims, rays, march, fwd_out["ckpt"], K, g_d, g_s, tuning=tune, ws=ws_r,
-                       out=bwd_out)
-        if ev:
-            ev[3].record(stream)
-
+    # the step: index + forward with checkpoints + backward, captured once and replayed
+    with torch.cuda.stream(stream):
+        batch.step(tune, stream=stream)
+    torch.cuda.synchronize()
+    E = [int(x) for x in batch.buf["totals"].cpu().tolist()]
+    for e, cap in zip(E, batch.caps):
+        assert e <= cap, "index capacity exceeded"
+    batch.capture(tune, stream=stream)
     for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        batch.replay(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
+    for _ in range(args.steps):
+        batch.replay(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    batch.release_graph()
+
+    # per-stage kernel time (HIP events on the launch stream), eager
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    with torch.cuda.stream(stream):
+        for i in range(args.steps):
+            evs[i][0].record(stream)
+            batch.build_index(stream=stream)
+            evs[i][1].record(stream)
+            batch.render_fwd(tune, stream=stream)
+            evs[i][2].record(stream)
+            batch.render_bwd(tune, stream=stream)
+            evs[i][3].record(stream)
+    torch.cuda.synchronize()
     t_idx = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     t_fwd = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     t_bwd = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
-    ms_step = wall * 1e3 / args.steps
 
-    # plain forward (no checkpoints) beside the differentiable one
-    plain = api.render_fwd(grid, idx, prims, rays, march, ckpt_every=0, tuning=tune, ws=ws_r)
+    # the plain per-scene forward (no checkpoints) beside the differentiable and batched forms
+    plain = []
+    for s, (p, r) in zip(scenes, dprims):
+        idx = api.build_index(grid, p)
+        plain.append((p, r, idx, api.render_fwd(grid, idx, p, r, march, ckpt_every=0,
+                                                 tuning=api.Tuning(tune.tile_w, tune.waves_per_block))))
     torch.cuda.synchronize()
     pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    pe[0].record(stream)
+    pe[0].record()
     for _ in range(args.steps):
-        api.render_fwd(grid, idx, prims, rays, march, ckpt_every=0, tuning=tune, ws=ws_r, out=plain)
-    pe[1].record(stream)
+        for p, r, idx, out in plain:
+            api.render_fwd(grid, idx, p, r, march, ckpt_every=0, out=out,
+                           tuning=api.Tuning(tune.tile_w, tune.waves_per_block))
+    pe[1].record()
     torch.cuda.synchronize()
     t_plain = pe[0].elapsed_time(pe[1]) / args.steps
 
+    workload = (f"config {args.config}: {len(scenes)} scene(s), {sum(s.prims.n for s in scenes)} superquadrics "
+                f"({'/'.join(str(s.prims.n) for s in scenes)}), {sc0.rays.shape[0]} cameras x "
+                f"{sc0.rays.shape[2]}x{sc0.rays.shape[1]} rays per scene, L={Ls} in [{sc0.march.t_near}, "
+                f"{sc0.march.t_far}] m, C={C}, grid {'x'.join(map(str, sc0.grid.dims))} at {sc0.grid.voxel} m, "
+                f"N_v={sc0.grid.nv}; step = index + forward(checkpoints) + backward, one hipGraph replay")
     result = {
         "metric": METRIC,
         "value": R * Ls / (ms_step / 1e3),
@@ -204,42 +223,42 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"config {args.config}: {sc.rays.shape[0]} cameras x {sc.rays.shape[1]}x"
-                                f"{sc.rays.shape[2]} rays, {sc.prims.n} superquadrics, L={Ls} in "
-                                f"[{sc.march.t_near}, {sc.march.t_far}] m, C={C}, grid "
-                                f"{'x'.join(map(str, sc.grid.dims))} at {sc.grid.voxel} m, N_v={sc.grid.nv}; "
-                                "step = index + forward(ckpt) + backward"),
-                   "rays": R, "samples_per_ray": Ls, "superquadrics": sc.prims.n, "classes": C,
-                   "ckpt_every": K, "tile_w": args.tile_w, "waves_per_block": args.wpb,
-                   "bwd_mode": args.bwd_mode},
+        "config": {"workload": workload, "scenes": len(scenes), "rays": R, "samples_per_ray": Ls,
+                   "superquadrics": sum(s.prims.n for s in scenes), "classes": C,
+                   "tuning": dict(tile_w=tune.tile_w, waves_per_block=tune.waves_per_block,
+                                  bwd_mode=tune.bwd_mode, persistent=tune.persistent,
+                                  chunk=tune.chunk or args.ckpt_every),
+                   "autotuned": bool(args.autotune)},
         "fwd_ray_samples_per_s": R * Ls / (t_fwd / 1e3),
         "plain_fwd_ray_samples_per_s": R * Ls / (t_plain / 1e3),
         "rays_per_s_fwd_bwd": R / (ms_step / 1e3),
         "index_ms": t_idx, "fwd_ms": t_fwd, "bwd_ms": t_bwd, "plain_fwd_ms": t_plain,
-        "index_entries": E,
+        "index_entries": sum(E),
     }
+    if tuned_ms is not None:
+        result["autotune_ms"] = [round(m, 3) for m in tuned_ms]
 
+    K = tune.chunk or args.ckpt_every
     if not args.no_stats:
-        st = api.render_fwd(grid, idx, prims, rays, march, ckpt_every=0, tuning=tune, ws=ws_r, stats=True)
-        bst = api.render_bwd_stats(grid, idx, prims, rays, march, fwd_out["ckpt"], K, g_d, g_s, tuning=tune,
-                                   ws=ws_r) if hasattr(api, "render_bwd_stats") else None
+        st = torch.zeros(4, dtype=torch.int64, device=dev)
+        bst = torch.zeros(6, dtype=torch.int64, device=dev)
+        with torch.cuda.stream(stream):
+            batch.render_fwd(tune, stats=st, stream=stream)
+            batch.render_bwd(tune, stats=bst, stream=stream)
         torch.cuda.synchronize()
-        s = st["stats"].cpu().numpy()
+        s = st.cpu().numpy()
         fst = dict(samples=int(s[0]), listed=int(s[1]), evaluated=int(s[2]))
+        b = dict(zip(api.BWD_STAT_NAMES, [int(v) for v in bst.cpu().numpy()]))
         result["units_fwd"] = fst
-        f_fwd = flops_fwd(fst, C)
-        result["fwd_tflops"] = f_fwd / (t_plain / 1e3) / 1e12
-        if bst is not None:
-            b = {k: int(v) for k, v in bst.items()}
-            result["units_bwd"] = b
-            f_bwd = flops_bwd(fst, b, C)
-            ach = f_bwd / (t_bwd / 1e3) / 1e12
-            kname = f"sqr::k_render_bwd_km<{api_cp(C)}, {K}, false>"
-            result["roofline"] = {"bound": "alu", "kernel": kname, "achieved": ach,
-                                  "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
-                                  "traffic": recorded_traffic(kname), "flop_per_launch": f_bwd,
-                                  "kernel_ms": t_bwd}
+        result["units_bwd"] = b
+        result["fwd_tflops"] = flops_fwd(fst, C) / (t_fwd / 1e3) / 1e12
         result["fwd_roofline_frac"] = result["fwd_tflops"] / VALU_PEAK_TFLOPS
+        f_bwd = flops_bwd(fst, b, C)
+        ach = f_bwd / (t_bwd / 1e3) / 1e12
+        kname = f"sqr::k_render_bwd_km<{api_cp(C)}, {K}, false, {'true' if tune.persistent else 'false'}>"
+        result["roofline"] = {"bound": "alu", "kernel": kname, "achieved": ach, "peak": VALU_PEAK_TFLOPS,
+                              "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
+                              "traffic": recorded_traffic(kname), "flop_per_launch": f_bwd, "kernel_ms": t_bwd}
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
@@ -251,7 +270,7 @@ def main():
         result["calib_copy_bytes"] = 4 * n
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(sc, args.cpu_rays)
+        result["cpu_baseline"] = cpu_baseline(sc0, args.cpu_rays)
     print(json.dumps(result), flush=True)
 
 

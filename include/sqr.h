@@ -123,13 +123,24 @@ typedef struct {
     float* logits;   /* [n,C] */
 } sq_grads;
 
-/* Kernel launch choices.  tile_w: ray-tile width in pixels (4, 8 or 16; a
- * tile is 64 pixels = one wavefront).  waves_per_block: 1..4.  bwd_mode:
- * SQ_BWD_AUTO picks the primitive-major backward when it applies
- * (ckpt_every in {4, 8}, grid within 2047 x 2047 x 511, per-wave id bitmap
- * within the LDS budget) and the sample-major one otherwise; the other two
- * values force one of them (forcing primitive-major where it does not apply
- * returns SQ_ERR_UNSUPPORTED).  Passing NULL uses sq_default_tuning(). */
+/* Kernel launch choices.
+ *  tile_w           ray-tile width in pixels: 4, 8 or 16 (a tile is 64 pixels,
+ *                   one wavefront).
+ *  waves_per_block  1..4.
+ *  bwd_mode         SQ_BWD_AUTO picks the primitive-major backward where it
+ *                   applies (checkpoint spacing 4 or 8, grid within
+ *                   2047 x 2047 x 511, per-wave id bitmap within 64 KiB of LDS
+ *                   per block) and the sample-major one otherwise; the other
+ *                   values force one of them (forcing primitive-major where it
+ *                   does not apply returns SQ_ERR_UNSUPPORTED).
+ *  persistent       0: one wavefront per ray tile; 1: persistent wavefronts
+ *                   that take tiles from eight per-XCD work queues (each XCD
+ *                   drains a contiguous range of tiles, then steals).
+ *  chunk            batched calls: checkpoint spacing K (4, 8 or 16) used by
+ *                   the forward's checkpoints and the backward; 0 = the
+ *                   batch's march.ckpt_every.  Single-scene calls always use
+ *                   march->ckpt_every.
+ * Passing NULL uses sq_default_tuning(). */
 #define SQ_BWD_AUTO 0
 #define SQ_BWD_SAMPLE_MAJOR 1
 #define SQ_BWD_PRIMITIVE_MAJOR 2
@@ -137,6 +148,8 @@ typedef struct {
     int32_t tile_w;
     int32_t waves_per_block;
     int32_t bwd_mode;
+    int32_t persistent;
+    int32_t chunk;
 } sq_tuning;
 
 /* Thread-local description of the last failure on this thread ("" if none). */
@@ -204,6 +217,92 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
                         const float* ckpt, const float* g_depth, const float* g_sem,
                         const sq_grads* grads, int64_t* stats, const sq_tuning* tuning,
                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: several scenes that share one grid, one ray march and one
+ * class count, with uneven primitive and camera counts, rendered by single
+ * launches whose wavefronts cover the tiles of every scene.
+ * ------------------------------------------------------------------------ */
+#define SQ_MAX_SCENES 32
+
+typedef struct {
+    int32_t n_prims;         /* primitives of the scene */
+    int32_t n_cams, height, width;
+    int64_t index_capacity;  /* id slots reserved for this scene's lists */
+} sq_scene;
+
+typedef struct {
+    int32_t  n_scenes;       /* 1 .. SQ_MAX_SCENES */
+    int32_t  n_classes;
+    sq_grid  grid;           /* shared by all scenes */
+    sq_march march;          /* shared; ckpt_every = default chunk */
+    sq_scene scenes[SQ_MAX_SCENES];
+} sq_batch;
+
+/* Device arrays of a batch, each concatenated scene-major in scene order:
+ *  means..logits [sum n_prims, .]; origins, dirs [sum rays, 3] (each scene
+ *  [n_cams, H, W, 3]); counts, offsets [n_scenes * V] (V = voxels; offsets are
+ *  relative to the scene's own id region); ids [sum index_capacity];
+ *  totals [n_scenes] (E per scene); depth, t_final [sum rays]; sem, probs
+ *  [sum rays * C] (each scene [n_cams, C, H, W]; probs nullable); ckpt
+ *  [ceil(L/K) * sum rays] (each scene [ceil(L/K), its rays]); g_depth, g_sem
+ *  shaped like depth and sem (nullable = zero); g_* shaped like the
+ *  parameters.  A call reads and writes only the members it needs. */
+typedef struct {
+    const float *means, *quats, *scales, *eps, *opacity, *logits;
+    const float *origins, *dirs;
+    int32_t *counts, *offsets, *ids;
+    int64_t *totals;
+    float *depth, *sem, *probs, *t_final, *ckpt;
+    const float *g_depth, *g_sem;
+    float *g_means, *g_quats, *g_scales, *g_eps, *g_opacity, *g_logits;
+} sq_batch_io;
+
+/* Bytes of workspace every batched call needs (host-only; 0 on bad input). */
+size_t sq_batch_workspace(const sq_batch* batch);
+
+/* sq_build_index for every scene of the batch (Sec. 3.3 "Preliminary
+ * Construction").  Writes counts, offsets, ids (below each scene's capacity)
+ * and totals. */
+sq_status sq_batch_build_index(const sq_batch* batch, const sq_batch_io* io,
+                               void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* sq_render_fwd for every scene of the batch in one launch (Sec. 3.3
+ * "Forward Pass"); checkpoints are written when io->ckpt is not NULL.
+ * `stats` as for sq_render_fwd. */
+sq_status sq_batch_render_fwd(const sq_batch* batch, const sq_batch_io* io, int64_t* stats,
+                              const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* sq_render_bwd for every scene of the batch in one launch (Sec. 3.3
+ * "Backward Pass"); needs the checkpoints of sq_batch_render_fwd with the
+ * same chunk.  `stats` as for sq_render_bwd. */
+sq_status sq_batch_render_bwd(const sq_batch* batch, const sq_batch_io* io, int64_t* stats,
+                              const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One training step of the renderer: index, forward with checkpoints,
+ * backward (every output of io is written). */
+sq_status sq_batch_step(const sq_batch* batch, const sq_batch_io* io, const sq_tuning* tuning,
+                        void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Captures sq_batch_step on `stream` (not the legacy default stream) into a
+ * hipGraph and instantiates it.  The graph keeps every pointer of io and ws:
+ * replays read the current contents of the same buffers.  The step contains
+ * no memset nodes and no host copies.  Free with sq_graph_destroy. */
+typedef struct sq_graph_impl* sq_graph;
+sq_status sq_batch_step_graph_create(const sq_batch* batch, const sq_batch_io* io, const sq_tuning* tuning,
+                                     void* ws, size_t ws_bytes, hipStream_t stream, sq_graph* out);
+sq_status sq_graph_launch(sq_graph graph, hipStream_t stream);
+sq_status sq_graph_destroy(sq_graph graph);
+
+/* Times sq_batch_step for every candidate tuning (one warm-up, then `reps`
+ * timed steps, HIP events on `stream`) and returns the fastest in
+ * *best_index and each candidate's mean step time in ms_per_candidate
+ * (nullable, n_candidates floats).  SYNCHRONOUS: waits for the stream.  All
+ * candidates are validated before the first launch.  The ckpt buffer must
+ * hold ceil(L/K) * sum rays floats for the smallest chunk K among them. */
+sq_status sq_batch_autotune(const sq_batch* batch, const sq_batch_io* io, const sq_tuning* candidates,
+                            int32_t n_candidates, int32_t reps, int32_t* best_index, float* ms_per_candidate,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

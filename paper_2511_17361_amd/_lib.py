@@ -22,6 +22,8 @@ SQ_MAX_CLASSES = 32
 EXPORTED = [
     "sq_last_error", "sq_version", "sq_default_tuning", "sq_index_capacity_bound",
     "sq_build_index_workspace", "sq_build_index", "sq_render_workspace", "sq_render_fwd", "sq_render_bwd",
+    "sq_batch_workspace", "sq_batch_build_index", "sq_batch_render_fwd", "sq_batch_render_bwd", "sq_batch_step",
+    "sq_batch_step_graph_create", "sq_graph_launch", "sq_graph_destroy", "sq_batch_autotune",
 ]
 
 
@@ -60,7 +62,28 @@ SQ_BWD_PRIMITIVE_MAJOR = 2
 
 
 class SqTuning(ct.Structure):
-    _fields_ = [("tile_w", ct.c_int32), ("waves_per_block", ct.c_int32), ("bwd_mode", ct.c_int32)]
+    _fields_ = [("tile_w", ct.c_int32), ("waves_per_block", ct.c_int32), ("bwd_mode", ct.c_int32),
+                ("persistent", ct.c_int32), ("chunk", ct.c_int32)]
+
+
+SQ_MAX_SCENES = 32
+
+
+class SqScene(ct.Structure):
+    _fields_ = [("n_prims", ct.c_int32), ("n_cams", ct.c_int32), ("height", ct.c_int32), ("width", ct.c_int32),
+                ("index_capacity", ct.c_int64)]
+
+
+class SqBatch(ct.Structure):
+    _fields_ = [("n_scenes", ct.c_int32), ("n_classes", ct.c_int32), ("grid", SqGrid), ("march", SqMarch),
+                ("scenes", SqScene * SQ_MAX_SCENES)]
+
+
+class SqBatchIO(ct.Structure):
+    _fields_ = [(n, ct.c_void_p) for n in (
+        "means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs",
+        "counts", "offsets", "ids", "totals", "depth", "sem", "probs", "t_final", "ckpt",
+        "g_depth", "g_sem", "g_means", "g_quats", "g_scales", "g_eps", "g_opacity", "g_logits")]
 
 
 _lib = None
@@ -95,6 +118,25 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.sq_render_bwd.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch),
                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, P(SqGrads), ct.c_void_p, P(SqTuning),
                                   ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_batch_workspace.restype = ct.c_size_t
+    lib.sq_batch_workspace.argtypes = [P(SqBatch)]
+    lib.sq_batch_build_index.restype = ct.c_int32
+    lib.sq_batch_build_index.argtypes = [P(SqBatch), P(SqBatchIO), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    for fn in (lib.sq_batch_render_fwd, lib.sq_batch_render_bwd):
+        fn.restype = ct.c_int32
+        fn.argtypes = [P(SqBatch), P(SqBatchIO), ct.c_void_p, P(SqTuning), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_batch_step.restype = ct.c_int32
+    lib.sq_batch_step.argtypes = [P(SqBatch), P(SqBatchIO), P(SqTuning), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_batch_step_graph_create.restype = ct.c_int32
+    lib.sq_batch_step_graph_create.argtypes = [P(SqBatch), P(SqBatchIO), P(SqTuning), ct.c_void_p, ct.c_size_t,
+                                               ct.c_void_p, P(ct.c_void_p)]
+    lib.sq_graph_launch.restype = ct.c_int32
+    lib.sq_graph_launch.argtypes = [ct.c_void_p, ct.c_void_p]
+    lib.sq_graph_destroy.restype = ct.c_int32
+    lib.sq_graph_destroy.argtypes = [ct.c_void_p]
+    lib.sq_batch_autotune.restype = ct.c_int32
+    lib.sq_batch_autotune.argtypes = [P(SqBatch), P(SqBatchIO), P(SqTuning), ct.c_int32, ct.c_int32,
+                                      P(ct.c_int32), P(ct.c_float), ct.c_void_p, ct.c_size_t, ct.c_void_p]
     _lib = lib
     return lib
 

@@ -136,12 +136,16 @@ class Tuning:
     tile_w: int = 8
     waves_per_block: int = 4
     bwd_mode: int = L.SQ_BWD_AUTO
+    persistent: int = 0
+    chunk: int = 0
 
     def c(self) -> L.SqTuning:
         t = L.SqTuning()
         t.tile_w = int(self.tile_w)
         t.waves_per_block = int(self.waves_per_block)
         t.bwd_mode = int(self.bwd_mode)
+        t.persistent = int(self.persistent)
+        t.chunk = int(self.chunk)
         return t
 
 
@@ -284,3 +288,185 @@ def render_bwd_stats(grid, index: Index, prims: Prims, rays: Rays, march, ckpt, 
                ws=ws, stats=st)
     vals = st.cpu().tolist()
     return dict(zip(BWD_STAT_NAMES, vals))
+
+
+# ---------------------------------------------------------------------------
+# Batched form
+# ---------------------------------------------------------------------------
+
+_IO_FIELDS = ("means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs", "counts", "offsets", "ids",
+              "totals", "depth", "sem", "probs", "t_final", "ckpt", "g_depth", "g_sem", "g_means", "g_quats",
+              "g_scales", "g_eps", "g_opacity", "g_logits")
+
+
+class Batch:
+    """Several scenes sharing one grid, march and class count, concatenated
+    scene-major in device memory (the layout of sq_batch_io in include/sqr.h).
+
+    Owns every device buffer of a training step (inputs, index, outputs,
+    checkpoints, upstream and parameter gradients) and one workspace, so a
+    captured step graph stays valid for the lifetime of the object."""
+
+    def __init__(self, grid, march, scenes, device="cuda", min_chunk: int = 4, probs: bool = True):
+        """scenes: list of (Prims, Rays) with device tensors; march.ckpt_every is
+        the default chunk (4, 8 or 16)."""
+        lib = L.load()
+        self.grid, self.march = Grid.of(grid), March.of(march)
+        if not 1 <= len(scenes) <= L.SQ_MAX_SCENES:
+            raise ValueError("1..32 scenes")
+        C = scenes[0][0].n_classes
+        if any(p.n_classes != C for p, _ in scenes):
+            raise ValueError("all scenes need the same class count")
+        self.n_classes = C
+        self.device = device
+        b = L.SqBatch()
+        b.n_scenes = len(scenes)
+        b.n_classes = C
+        b.grid = self.grid.c()
+        b.march = self.march.c()
+        self.caps = []
+        for i, (p, r) in enumerate(scenes):
+            cams, H, W = r.shape
+            cap = capacity_bound(self.grid, p.n)
+            self.caps.append(cap)
+            b.scenes[i].n_prims = p.n
+            b.scenes[i].n_cams, b.scenes[i].height, b.scenes[i].width = cams, H, W
+            b.scenes[i].index_capacity = cap
+        self.c_batch = b
+        self.scene_shapes = [(p.n,) + tuple(r.shape) for p, r in scenes]
+        cat = lambda ts: torch.cat([t.reshape(-1) for t in ts]).contiguous()
+        self.prims = Prims(*(cat([getattr(p, k) for p, _ in scenes]).view(-1, *getattr(scenes[0][0], k).shape[1:])
+                             for k in ("means", "quats", "scales", "eps", "opacity", "logits")))
+        self.origins = cat([r.origins for _, r in scenes]).view(-1, 3)
+        self.dirs = cat([r.dirs for _, r in scenes]).view(-1, 3)
+        R = self.origins.shape[0]
+        V = self.grid.n_voxels
+        S = len(scenes)
+        nck = -(-self.march.n_samples // min_chunk)
+        z = lambda *shape, dt=torch.float32: torch.zeros(shape, dtype=dt, device=device)
+        self.buf = dict(counts=z(S * V, dt=torch.int32), offsets=z(S * V, dt=torch.int32),
+                        ids=z(max(sum(self.caps), 1), dt=torch.int32), totals=z(S, dt=torch.int64),
+                        depth=z(R), sem=z(R * C), probs=z(R * C) if probs else None, t_final=z(R), ckpt=z(nck * R),
+                        g_depth=z(R), g_sem=z(R * C))
+        for k in ("means", "quats", "scales", "eps", "opacity", "logits"):
+            self.buf["g_" + k] = torch.zeros_like(getattr(self.prims, k))
+        self.ws = _workspace(lib.sq_batch_workspace(ct.byref(b)), device)
+        self.graph = None
+
+    @property
+    def n_rays(self) -> int:
+        return int(self.origins.shape[0])
+
+    def io(self) -> L.SqBatchIO:
+        io = L.SqBatchIO()
+        vals = dict(self.buf)
+        for k in ("means", "quats", "scales", "eps", "opacity", "logits"):
+            vals[k] = getattr(self.prims, k)
+        vals["origins"], vals["dirs"] = self.origins, self.dirs
+        for name in _IO_FIELDS:
+            setattr(io, name, _ptr(vals.get(name)))
+        return io
+
+    def _call(self, fn, *args):
+        L.check(fn(ct.byref(self.c_batch), ct.byref(self.io()), *args))
+
+    def build_index(self, stream=None):
+        lib = L.load()
+        self._call(lib.sq_batch_build_index, _ptr(self.ws), self.ws.numel(), _stream_handle(stream))
+
+    def render_fwd(self, tuning: Optional[Tuning] = None, stats=None, stream=None):
+        lib = L.load()
+        t = (tuning or Tuning()).c()
+        self._call(lib.sq_batch_render_fwd, _ptr(stats), ct.byref(t), _ptr(self.ws), self.ws.numel(),
+                   _stream_handle(stream))
+
+    def render_bwd(self, tuning: Optional[Tuning] = None, stats=None, stream=None):
+        lib = L.load()
+        t = (tuning or Tuning()).c()
+        self._call(lib.sq_batch_render_bwd, _ptr(stats), ct.byref(t), _ptr(self.ws), self.ws.numel(),
+                   _stream_handle(stream))
+
+    def step(self, tuning: Optional[Tuning] = None, stream=None):
+        lib = L.load()
+        t = (tuning or Tuning()).c()
+        self._call(lib.sq_batch_step, ct.byref(t), _ptr(self.ws), self.ws.numel(), _stream_handle(stream))
+
+    def capture(self, tuning: Optional[Tuning] = None, stream=None):
+        """Capture one step into a hipGraph on `stream` (a non-default torch stream)."""
+        lib = L.load()
+        self.release_graph()
+        t = (tuning or Tuning()).c()
+        h = ct.c_void_p()
+        stream = stream or torch.cuda.Stream(device=self.device)
+        L.check(lib.sq_batch_step_graph_create(ct.byref(self.c_batch), ct.byref(self.io()), ct.byref(t),
+                                               _ptr(self.ws), self.ws.numel(), _stream_handle(stream),
+                                               ct.byref(h)))
+        self.graph = h
+        self.graph_stream = stream
+        return stream
+
+    def replay(self, stream=None):
+        lib = L.load()
+        if self.graph is None:
+            raise RuntimeError("no captured graph")
+        L.check(lib.sq_graph_launch(self.graph, _stream_handle(stream or self.graph_stream)))
+
+    def release_graph(self):
+        if getattr(self, "graph", None) is not None:
+            L.load().sq_graph_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.release_graph()
+        except Exception:
+            pass
+
+    def autotune(self, candidates, reps: int = 2, stream=None):
+        """Time a step for every candidate Tuning; returns (best Tuning, ms list). Synchronous."""
+        lib = L.load()
+        n = len(candidates)
+        arr = (L.SqTuning * n)(*[c.c() for c in candidates])
+        best = ct.c_int32(-1)
+        ms = (ct.c_float * n)()
+        L.check(lib.sq_batch_autotune(ct.byref(self.c_batch), ct.byref(self.io()), arr, n, int(reps),
+                                      ct.byref(best), ms, _ptr(self.ws), self.ws.numel(), _stream_handle(stream)))
+        return candidates[best.value], list(ms)
+
+    # ---- views of one scene's slice of the concatenated outputs ----
+    def scene_slices(self, i):
+        n_before = sum(s[0] for s in self.scene_shapes[:i])
+        r_before = sum(s[1] * s[2] * s[3] for s in self.scene_shapes[:i])
+        n, cams, H, W = self.scene_shapes[i]
+        return n_before, n, r_before, cams, H, W
+
+    def scene_outputs(self, i):
+        n0, n, r0, cams, H, W = self.scene_slices(i)
+        R = cams * H * W
+        C = self.n_classes
+        out = dict(depth=self.buf["depth"][r0:r0 + R].view(cams, H, W),
+                   t_final=self.buf["t_final"][r0:r0 + R].view(cams, H, W),
+                   sem=self.buf["sem"][r0 * C:(r0 + R) * C].view(cams, C, H, W))
+        if self.buf.get("probs") is not None:
+            out["probs"] = self.buf["probs"][r0 * C:(r0 + R) * C].view(cams, C, H, W)
+        for k in ("means", "quats", "scales", "eps", "opacity", "logits"):
+            out["g_" + k] = self.buf["g_" + k][n0:n0 + n]
+        return out
+
+    def set_upstream(self, i, g_depth, g_sem):
+        n0, n, r0, cams, H, W = self.scene_slices(i)
+        R = cams * H * W
+        C = self.n_classes
+        self.buf["g_depth"][r0:r0 + R] = g_depth.reshape(-1)
+        self.buf["g_sem"][r0 * C:(r0 + R) * C] = g_sem.reshape(-1)
+
+
+def default_candidates():
+    """Tile width x waves per block x chunk x persistent waves."""
+    out = []
+    for tw in (8, 16, 4):
+        for wpb in (4, 2):
+            for chunk in (4, 8):
+                for pers in (0, 1):
+                    out.append(Tuning(tile_w=tw, waves_per_block=wpb, chunk=chunk, persistent=pers))
+    return out

@@ -1,11 +1,14 @@
 // C ABI of the renderer: host-side validation, workspace queries and dispatch
-// to the kernel launchers.  Nothing is launched for a rejected call.
+// to the kernel launchers.  Nothing is launched for a rejected call.  Every
+// call is a batch of scenes internally; the single-scene entry points build a
+// batch of one.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 
 #include "../../include/sqr.h"
 #include "sqr_internal.h"
@@ -39,6 +42,13 @@ bool grid_ok(const sq_grid* g) {
     return std::isfinite(g->voxel) && g->voxel > 0.0f && g->nv >= 0 && g->nv <= 32767;
 }
 
+sq_status check_grid(const sq_grid* g) {
+    if (!grid_ok(g)) return fail(SQ_ERR_INVALID, "invalid grid (dims in [1,32767], voxel > 0, nv >= 0)");
+    if ((int64_t)g->dims[0] * g->dims[1] * g->dims[2] >= ((int64_t)1 << 31))
+        return fail(SQ_ERR_INVALID, "grid has >= 2^31 voxels");
+    return SQ_OK;
+}
+
 sqr::GridDev to_dev(const sq_grid* g) {
     sqr::GridDev d;
     d.lox = g->lo[0]; d.loy = g->lo[1]; d.loz = g->lo[2];
@@ -46,31 +56,6 @@ sqr::GridDev to_dev(const sq_grid* g) {
     d.X = g->dims[0]; d.Y = g->dims[1]; d.Z = g->dims[2];
     d.nv = g->nv;
     return d;
-}
-
-int64_t nvox(const sq_grid* g) { return (int64_t)g->dims[0] * g->dims[1] * g->dims[2]; }
-
-sq_status check_prims(const sq_prims* p, bool need_params) {
-    if (!p) return fail(SQ_ERR_INVALID, "prims is NULL");
-    if (p->n < 0) return fail(SQ_ERR_INVALID, "prims->n = %d < 0", p->n);
-    if (p->n_classes < 1 || p->n_classes > SQ_MAX_CLASSES)
-        return fail(SQ_ERR_INVALID, "n_classes = %d outside [1, %d]", p->n_classes, SQ_MAX_CLASSES);
-    if (p->n > 0) {
-        if (!p->means) return fail(SQ_ERR_INVALID, "prims->means is NULL");
-        if (need_params && (!p->quats || !p->scales || !p->eps || !p->opacity || !p->logits))
-            return fail(SQ_ERR_INVALID, "a primitive parameter array is NULL");
-    }
-    return SQ_OK;
-}
-
-sq_status check_rays(const sq_rays* r) {
-    if (!r) return fail(SQ_ERR_INVALID, "rays is NULL");
-    if (r->n_cams < 0 || r->height < 0 || r->width < 0)
-        return fail(SQ_ERR_INVALID, "negative ray dimensions");
-    const int64_t n = (int64_t)r->n_cams * r->height * r->width;
-    if (n > ((int64_t)1 << 31) / 32) return fail(SQ_ERR_INVALID, "too many rays (%lld)", (long long)n);
-    if (n > 0 && (!r->origins || !r->dirs)) return fail(SQ_ERR_INVALID, "ray origins/dirs is NULL");
-    return SQ_OK;
 }
 
 sq_status check_march(const sq_march* m) {
@@ -85,15 +70,210 @@ sq_status check_march(const sq_march* m) {
     return SQ_OK;
 }
 
-sqr::MarchDev to_dev(const sq_march* m) {
+sqr::MarchDev to_dev(const sq_march* m, int K) {
     sqr::MarchDev d;
     d.L = m->n_samples;
     d.t_near = m->t_near;
     // delta = fl32(fl32(t_far - t_near) / fl32(L - 1)), as the pinned sample sequence states
     const float span = m->t_far - m->t_near;
     d.delta = m->n_samples > 1 ? span / (float)(m->n_samples - 1) : 0.0f;
-    d.K = m->ckpt_every;
+    d.K = K;
     return d;
+}
+
+sq_tuning default_tuning() {
+    sq_tuning t;
+    t.tile_w = 8;
+    t.waves_per_block = 4;
+    t.bwd_mode = SQ_BWD_AUTO;
+    t.persistent = 0;
+    t.chunk = 0;
+    return t;
+}
+
+sq_status tuning_of(const sq_tuning* t, sqr::TuneDev& d) {
+    sq_tuning v = t ? *t : default_tuning();
+    if (!(v.tile_w == 4 || v.tile_w == 8 || v.tile_w == 16))
+        return fail(SQ_ERR_INVALID, "tile_w = %d not in {4, 8, 16}", v.tile_w);
+    if (v.waves_per_block < 1 || v.waves_per_block > 4)
+        return fail(SQ_ERR_INVALID, "waves_per_block = %d not in [1, 4]", v.waves_per_block);
+    if (v.bwd_mode < SQ_BWD_AUTO || v.bwd_mode > SQ_BWD_PRIMITIVE_MAJOR)
+        return fail(SQ_ERR_INVALID, "bwd_mode = %d not in {0, 1, 2}", v.bwd_mode);
+    if (v.persistent < 0 || v.persistent > 1) return fail(SQ_ERR_INVALID, "persistent must be 0 or 1");
+    if (v.chunk < 0) return fail(SQ_ERR_INVALID, "chunk < 0");
+    d.tile_w = v.tile_w;
+    d.waves_per_block = v.waves_per_block;
+    d.bwd_mode = v.bwd_mode;
+    d.persistent = v.persistent;
+    return SQ_OK;
+}
+
+// A validated batch: host description plus the per-call constants.
+struct Plan {
+    sqr::GridDev g;
+    sqr::BatchDesc d;
+    sq_march m;
+};
+
+sq_status make_plan(const sq_batch* b, int tile_w, Plan& p) {
+    if (!b) return fail(SQ_ERR_INVALID, "batch is NULL");
+    sq_status s;
+    if ((s = check_grid(&b->grid))) return s;
+    if ((s = check_march(&b->march))) return s;
+    if (b->n_scenes < 1 || b->n_scenes > SQ_MAX_SCENES)
+        return fail(SQ_ERR_INVALID, "n_scenes = %d outside [1, %d]", b->n_scenes, SQ_MAX_SCENES);
+    if (b->n_classes < 1 || b->n_classes > SQ_MAX_CLASSES)
+        return fail(SQ_ERR_INVALID, "n_classes = %d outside [1, %d]", b->n_classes, SQ_MAX_CLASSES);
+    std::memset(&p.d, 0, sizeof(p.d));
+    p.d.n_scenes = b->n_scenes;
+    p.d.C = b->n_classes;
+    int64_t prims = 0, rays = 0;
+    for (int i = 0; i < b->n_scenes; ++i) {
+        const sq_scene& sc = b->scenes[i];
+        if (sc.n_prims < 0 || sc.n_cams < 0 || sc.height < 0 || sc.width < 0)
+            return fail(SQ_ERR_INVALID, "scene %d: negative size", i);
+        if (sc.index_capacity < 0) return fail(SQ_ERR_INVALID, "scene %d: index_capacity < 0", i);
+        prims += sc.n_prims;
+        rays += (int64_t)sc.n_cams * sc.height * sc.width;
+        if (prims >= ((int64_t)1 << 30)) return fail(SQ_ERR_INVALID, "too many primitives");
+        if (rays > ((int64_t)1 << 31) / 32) return fail(SQ_ERR_INVALID, "too many rays (%lld)", (long long)rays);
+        sqr::SceneDev& S = p.d.s[i];
+        S.n = sc.n_prims;
+        S.cams = sc.n_cams;
+        S.H = sc.height;
+        S.W = sc.width;
+        S.cap = sc.index_capacity;
+    }
+    sqr::finish_desc(p.d, tile_w);
+    p.g = to_dev(&b->grid);
+    p.m = b->march;
+    return SQ_OK;
+}
+
+sq_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (need > 0 && (!ws || ws_bytes < need))
+        return fail(SQ_ERR_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)ws % sqr::WS_ALIGN) return fail(SQ_ERR_INVALID, "workspace must be 256-byte aligned");
+    return SQ_OK;
+}
+
+sq_status check_io_index(const Plan& p, const sq_batch_io* io) {
+    if (!io) return fail(SQ_ERR_INVALID, "io is NULL");
+    if (!io->counts || !io->offsets) return fail(SQ_ERR_INVALID, "index counts/offsets is NULL");
+    int64_t cap = 0;
+    for (int i = 0; i < p.d.n_scenes; ++i) cap += p.d.s[i].cap;
+    if (cap > 0 && !io->ids) return fail(SQ_ERR_INVALID, "index ids is NULL");
+    if (p.d.total_prims > 0 && !io->means) return fail(SQ_ERR_INVALID, "means is NULL");
+    return SQ_OK;
+}
+
+sq_status check_io_render(const Plan& p, const sq_batch_io* io) {
+    sq_status s;
+    if ((s = check_io_index(p, io))) return s;
+    if (p.d.total_prims > 0 && (!io->quats || !io->scales || !io->eps || !io->opacity || !io->logits))
+        return fail(SQ_ERR_INVALID, "a primitive parameter array is NULL");
+    if (p.d.total_rays > 0 && (!io->origins || !io->dirs)) return fail(SQ_ERR_INVALID, "ray origins/dirs is NULL");
+    return SQ_OK;
+}
+
+int chunk_of(const sq_tuning* t, const sq_march& m) {
+    if (t && t->chunk > 0) return t->chunk;
+    return m.ckpt_every;
+}
+
+sqr::BatchIO to_dev(const sq_batch_io* io) {
+    sqr::BatchIO b;
+    std::memset(&b, 0, sizeof(b));
+    b.means = io->means; b.quats = io->quats; b.scales = io->scales; b.eps = io->eps;
+    b.opacity = io->opacity; b.logits = io->logits; b.origins = io->origins; b.dirs = io->dirs;
+    b.counts = io->counts; b.offsets = io->offsets; b.ids = io->ids; b.totals = io->totals;
+    b.depth = io->depth; b.sem = io->sem; b.probs = io->probs; b.t_final = io->t_final; b.ckpt = io->ckpt;
+    b.g_depth = io->g_depth; b.g_sem = io->g_sem;
+    b.g_means = io->g_means; b.g_quats = io->g_quats; b.g_scales = io->g_scales; b.g_eps = io->g_eps;
+    b.g_opacity = io->g_opacity; b.g_logits = io->g_logits;
+    return b;
+}
+
+sq_status index_checked(const Plan& p, const sq_batch_io* io, void* ws, size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_io_index(p, io))) return s;
+    if (!io->totals) return fail(SQ_ERR_INVALID, "index totals is NULL");
+    if ((s = check_ws(ws, ws_bytes, sqr::index_workspace_bytes(p.g, p.d)))) return s;
+    return hip_status(sqr::launch_batch_index(p.g, p.d, to_dev(io), ws, stream), "build_index");
+}
+
+sq_status fwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, const sq_tuning* tuning, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_io_render(p, io))) return s;
+    if (p.d.total_rays > 0 && (!io->depth || !io->sem || !io->t_final))
+        return fail(SQ_ERR_INVALID, "depth/sem/t_final is NULL");
+    const int K = chunk_of(tuning, p.m);
+    if (io->ckpt && K < 1) return fail(SQ_ERR_INVALID, "ckpt given but the checkpoint spacing is < 1");
+    sqr::TuneDev tune;
+    if ((s = tuning_of(tuning, tune))) return s;
+    if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+    const hipError_t e = sqr::launch_batch_fwd(p.g, p.d, to_dev(&p.m, io->ckpt ? K : 0), to_dev(io), stats, tune,
+                                               ws, stream);
+    return hip_status(e, "render_fwd");
+}
+
+sq_status bwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, const sq_tuning* tuning, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_io_render(p, io))) return s;
+    const int K = chunk_of(tuning, p.m);
+    if (!(K == 4 || K == 8 || K == 16))
+        return fail(SQ_ERR_INVALID, "backward needs a checkpoint spacing in {4, 8, 16} (got %d)", K);
+    if (p.d.total_rays > 0 && !io->ckpt) return fail(SQ_ERR_INVALID, "ckpt is NULL");
+    if (p.d.total_prims > 0 && (!io->g_means || !io->g_quats || !io->g_scales || !io->g_eps || !io->g_opacity ||
+                                !io->g_logits))
+        return fail(SQ_ERR_INVALID, "a gradient output array is NULL");
+    sqr::TuneDev tune;
+    if ((s = tuning_of(tuning, tune))) return s;
+    if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
+        !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
+        return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply (chunk %d, max n %d)", K,
+                    p.d.max_n);
+    if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+    const hipError_t e = sqr::launch_batch_bwd(p.g, p.d, to_dev(&p.m, K), to_dev(io), stats, tune, ws, stream);
+    return hip_status(e, "render_bwd");
+}
+
+// ---- single-scene adapters --------------------------------------------------
+void one_scene(const sq_grid* grid, const sq_march* march, int n, int C, int cams, int H, int W, int64_t cap,
+               sq_batch& b) {
+    std::memset(&b, 0, sizeof(b));
+    b.n_scenes = 1;
+    b.n_classes = C;
+    b.grid = *grid;
+    b.march = *march;
+    b.scenes[0].n_prims = n;
+    b.scenes[0].n_cams = cams;
+    b.scenes[0].height = H;
+    b.scenes[0].width = W;
+    b.scenes[0].index_capacity = cap;
+}
+
+sq_status check_prims(const sq_prims* p, bool need_params) {
+    if (!p) return fail(SQ_ERR_INVALID, "prims is NULL");
+    if (p->n < 0) return fail(SQ_ERR_INVALID, "prims->n = %d < 0", p->n);
+    if (need_params && (p->n_classes < 1 || p->n_classes > SQ_MAX_CLASSES))
+        return fail(SQ_ERR_INVALID, "n_classes = %d outside [1, %d]", p->n_classes, SQ_MAX_CLASSES);
+    if (p->n > 0) {
+        if (!p->means) return fail(SQ_ERR_INVALID, "prims->means is NULL");
+        if (need_params && (!p->quats || !p->scales || !p->eps || !p->opacity || !p->logits))
+            return fail(SQ_ERR_INVALID, "a primitive parameter array is NULL");
+    }
+    return SQ_OK;
+}
+
+sq_status check_rays(const sq_rays* r) {
+    if (!r) return fail(SQ_ERR_INVALID, "rays is NULL");
+    if (r->n_cams < 0 || r->height < 0 || r->width < 0) return fail(SQ_ERR_INVALID, "negative ray dimensions");
+    const int64_t n = (int64_t)r->n_cams * r->height * r->width;
+    if (n > 0 && (!r->origins || !r->dirs)) return fail(SQ_ERR_INVALID, "ray origins/dirs is NULL");
+    return SQ_OK;
 }
 
 sq_status check_index(const sq_index* idx, bool for_render) {
@@ -105,40 +285,20 @@ sq_status check_index(const sq_index* idx, bool for_render) {
     return SQ_OK;
 }
 
-sq_status tuning_of(const sq_tuning* t, sqr::TuneDev& d) {
-    sq_tuning v = t ? *t : sq_default_tuning();
-    if (!(v.tile_w == 4 || v.tile_w == 8 || v.tile_w == 16))
-        return fail(SQ_ERR_INVALID, "tile_w = %d not in {4, 8, 16}", v.tile_w);
-    if (v.waves_per_block < 1 || v.waves_per_block > 4)
-        return fail(SQ_ERR_INVALID, "waves_per_block = %d not in [1, 4]", v.waves_per_block);
-    if (v.bwd_mode < SQ_BWD_AUTO || v.bwd_mode > SQ_BWD_PRIMITIVE_MAJOR)
-        return fail(SQ_ERR_INVALID, "bwd_mode = %d not in {0, 1, 2}", v.bwd_mode);
-    d.tile_w = v.tile_w;
-    d.waves_per_block = v.waves_per_block;
-    d.bwd_mode = v.bwd_mode;
-    return SQ_OK;
+void io_from(const sq_index* idx, const sq_prims* pr, const sq_rays* rays, sq_batch_io& io) {
+    std::memset(&io, 0, sizeof(io));
+    io.means = pr->means; io.quats = pr->quats; io.scales = pr->scales; io.eps = pr->eps;
+    io.opacity = pr->opacity; io.logits = pr->logits;
+    if (rays) { io.origins = rays->origins; io.dirs = rays->dirs; }
+    io.counts = idx->counts; io.offsets = idx->offsets; io.ids = idx->ids; io.totals = idx->total;
 }
 
-sqr::PrimsDev to_dev(const sq_prims* p) {
-    sqr::PrimsDev d;
-    d.n = p->n; d.C = p->n_classes;
-    d.means = p->means; d.quats = p->quats; d.scales = p->scales; d.eps = p->eps;
-    d.opacity = p->opacity; d.logits = p->logits;
-    return d;
-}
+struct GraphImpl {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
 
-sqr::RaysDev to_dev(const sq_rays* r) {
-    sqr::RaysDev d;
-    d.n_cams = r->n_cams; d.H = r->height; d.W = r->width;
-    d.origins = r->origins; d.dirs = r->dirs;
-    return d;
-}
-
-sqr::IndexDev to_dev(const sq_index* i) {
-    sqr::IndexDev d;
-    d.counts = i->counts; d.offsets = i->offsets; d.ids = i->ids; d.capacity = i->capacity;
-    return d;
-}
+const sq_march kIndexMarch = {1, 0.0f, 1.0f, 0};
 
 }  // namespace
 
@@ -146,15 +306,9 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 100; }
+int32_t sq_version(void) { return 200; }
 
-sq_tuning sq_default_tuning(void) {
-    sq_tuning t;
-    t.tile_w = 8;
-    t.waves_per_block = 4;
-    t.bwd_mode = SQ_BWD_AUTO;
-    return t;
-}
+sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
 int64_t sq_index_capacity_bound(const sq_grid* grid, int32_t n) {
     if (!grid_ok(grid) || n < 0) return -1;
@@ -168,87 +322,255 @@ int64_t sq_index_capacity_bound(const sq_grid* grid, int32_t n) {
 
 size_t sq_build_index_workspace(const sq_grid* grid, int32_t n) {
     if (!grid_ok(grid) || n < 0) return 0;
-    return sqr::index_workspace_bytes(nvox(grid), n);
+    sq_batch b;
+    one_scene(grid, &kIndexMarch, n, 1, 0, 0, 0, 0, b);
+    Plan p;
+    if (make_plan(&b, 8, p)) return 0;
+    return sqr::index_workspace_bytes(p.g, p.d);
 }
 
 sq_status sq_build_index(const sq_grid* grid, const sq_prims* prims, sq_index* idx, void* ws, size_t ws_bytes,
                          hipStream_t stream) {
-    if (!grid_ok(grid)) return fail(SQ_ERR_INVALID, "invalid grid (dims in [1,32767], voxel > 0, nv >= 0)");
-    if (!prims || prims->n < 0) return fail(SQ_ERR_INVALID, "invalid prims");
-    if (prims->n > 0 && !prims->means) return fail(SQ_ERR_INVALID, "prims->means is NULL");
-    sq_status s = check_index(idx, false);
-    if (s) return s;
-    if (nvox(grid) >= ((int64_t)1 << 31)) return fail(SQ_ERR_INVALID, "grid has >= 2^31 voxels");
-    const size_t need = sqr::index_workspace_bytes(nvox(grid), prims->n);
-    if (!ws || ws_bytes < need) return fail(SQ_ERR_CAPACITY, "index workspace %zu < %zu bytes", ws_bytes, need);
-    if ((uintptr_t)ws % sqr::WS_ALIGN) return fail(SQ_ERR_INVALID, "workspace must be 256-byte aligned");
-    const hipError_t e = sqr::launch_build_index(to_dev(grid), prims->means, prims->n, idx->counts, idx->offsets,
-                                                 idx->ids, idx->capacity, idx->total, ws, stream);
-    return hip_status(e, "sq_build_index");
+    sq_status s;
+    if ((s = check_grid(grid))) return s;
+    if ((s = check_prims(prims, false))) return s;
+    if ((s = check_index(idx, false))) return s;
+    sq_batch b;
+    one_scene(grid, &kIndexMarch, prims->n, 1, 0, 0, 0, idx->capacity, b);
+    Plan p;
+    if ((s = make_plan(&b, 8, p))) return s;
+    sq_batch_io io;
+    io_from(idx, prims, nullptr, io);
+    return index_checked(p, &io, ws, ws_bytes, stream);
 }
 
 size_t sq_render_workspace(const sq_grid* grid, const sq_prims* prims, const sq_rays* rays, const sq_march* march) {
-    (void)grid; (void)rays; (void)march;
-    if (!prims || prims->n < 0 || prims->n_classes < 1 || prims->n_classes > SQ_MAX_CLASSES) return 0;
-    return sqr::render_workspace_bytes(prims->n, prims->n_classes);
-}
-
-static sq_status check_render_common(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
-                                     const sq_rays* rays, const sq_march* march, void* ws, size_t ws_bytes) {
-    if (!grid_ok(grid)) return fail(SQ_ERR_INVALID, "invalid grid (dims in [1,32767], voxel > 0, nv >= 0)");
-    sq_status s;
-    if ((s = check_index(idx, true))) return s;
-    if ((s = check_prims(prims, true))) return s;
-    if ((s = check_rays(rays))) return s;
-    if ((s = check_march(march))) return s;
-    const size_t need = sqr::render_workspace_bytes(prims->n, prims->n_classes);
-    if (need > 0 && (!ws || ws_bytes < need))
-        return fail(SQ_ERR_CAPACITY, "render workspace %zu < %zu bytes", ws_bytes, need);
-    if ((uintptr_t)ws % sqr::WS_ALIGN) return fail(SQ_ERR_INVALID, "workspace must be 256-byte aligned");
-    return SQ_OK;
+    if (!grid_ok(grid) || !prims || prims->n < 0 || prims->n_classes < 1 || prims->n_classes > SQ_MAX_CLASSES)
+        return 0;
+    sq_batch b;
+    const sq_march m = march ? *march : kIndexMarch;
+    const int cams = rays ? rays->n_cams : 0, H = rays ? rays->height : 0, W = rays ? rays->width : 0;
+    one_scene(grid, &m, prims->n, prims->n_classes, cams, H, W, 0, b);
+    Plan p;
+    if (make_plan(&b, 8, p)) return 0;
+    return sqr::batch_workspace_bytes(p.g, p.d);
 }
 
 sq_status sq_render_fwd(const sq_grid* grid, const sq_index* idx, const sq_prims* prims, const sq_rays* rays,
                         const sq_march* march, float* depth, float* sem, float* probs, float* t_final, float* ckpt,
                         int64_t* stats, const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream) {
-    sq_status s = check_render_common(grid, idx, prims, rays, march, ws, ws_bytes);
-    if (s) return s;
-    const int64_t nr = (int64_t)rays->n_cams * rays->height * rays->width;
-    if (nr > 0 && (!depth || !sem || !t_final)) return fail(SQ_ERR_INVALID, "depth/sem/t_final is NULL");
-    if (ckpt && march->ckpt_every < 1) return fail(SQ_ERR_INVALID, "ckpt given but ckpt_every < 1");
+    sq_status s;
+    if ((s = check_grid(grid))) return s;
+    if ((s = check_index(idx, true))) return s;
+    if ((s = check_prims(prims, true))) return s;
+    if ((s = check_rays(rays))) return s;
+    if ((s = check_march(march))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
-    const hipError_t e = sqr::launch_render_fwd(to_dev(grid), to_dev(idx), to_dev(prims), to_dev(rays),
-                                                to_dev(march), depth, sem, probs, t_final, ckpt, stats, tune, ws,
-                                                stream);
-    return hip_status(e, "sq_render_fwd");
+    if (ckpt && march->ckpt_every < 1) return fail(SQ_ERR_INVALID, "ckpt given but ckpt_every < 1");
+    sq_batch b;
+    one_scene(grid, march, prims->n, prims->n_classes, rays->n_cams, rays->height, rays->width, idx->capacity, b);
+    Plan p;
+    if ((s = make_plan(&b, tune.tile_w, p))) return s;
+    sq_batch_io io;
+    io_from(idx, prims, rays, io);
+    io.depth = depth; io.sem = sem; io.probs = probs; io.t_final = t_final; io.ckpt = ckpt;
+    sq_tuning t = tuning ? *tuning : default_tuning();
+    t.chunk = march->ckpt_every;
+    return fwd_checked(p, &io, stats, &t, ws, ws_bytes, stream);
 }
 
 sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims* prims, const sq_rays* rays,
                         const sq_march* march, const float* ckpt, const float* g_depth, const float* g_sem,
                         const sq_grads* grads, int64_t* stats, const sq_tuning* tuning, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
-    sq_status s = check_render_common(grid, idx, prims, rays, march, ws, ws_bytes);
-    if (s) return s;
+    sq_status s;
+    if ((s = check_grid(grid))) return s;
+    if ((s = check_index(idx, true))) return s;
+    if ((s = check_prims(prims, true))) return s;
+    if ((s = check_rays(rays))) return s;
+    if ((s = check_march(march))) return s;
     if (!(march->ckpt_every == 4 || march->ckpt_every == 8 || march->ckpt_every == 16))
         return fail(SQ_ERR_INVALID, "backward needs ckpt_every in {4, 8, 16} (got %d)", march->ckpt_every);
     const int64_t nr = (int64_t)rays->n_cams * rays->height * rays->width;
     if (nr > 0 && !ckpt) return fail(SQ_ERR_INVALID, "ckpt is NULL");
     if (!grads) return fail(SQ_ERR_INVALID, "grads is NULL");
-    if (prims->n > 0 && (!grads->means || !grads->quats || !grads->scales || !grads->eps || !grads->opacity ||
-                         !grads->logits))
-        return fail(SQ_ERR_INVALID, "a gradient output array is NULL");
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
-    if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
-        !sqr::bwd_primitive_major_ok(to_dev(grid), prims->n, march->ckpt_every, tune.waves_per_block))
-        return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply (ckpt_every %d, n %d)",
-                    march->ckpt_every, prims->n);
-    const hipError_t e = sqr::launch_render_bwd(to_dev(grid), to_dev(idx), to_dev(prims), to_dev(rays),
-                                                to_dev(march), ckpt, g_depth, g_sem, grads->means, grads->quats,
-                                                grads->scales, grads->eps, grads->opacity, grads->logits, stats, tune, ws,
-                                                stream);
-    return hip_status(e, "sq_render_bwd");
+    sq_batch b;
+    one_scene(grid, march, prims->n, prims->n_classes, rays->n_cams, rays->height, rays->width, idx->capacity, b);
+    Plan p;
+    if ((s = make_plan(&b, tune.tile_w, p))) return s;
+    sq_batch_io io;
+    io_from(idx, prims, rays, io);
+    io.ckpt = const_cast<float*>(ckpt);
+    io.g_depth = g_depth; io.g_sem = g_sem;
+    io.g_means = grads->means; io.g_quats = grads->quats; io.g_scales = grads->scales; io.g_eps = grads->eps;
+    io.g_opacity = grads->opacity; io.g_logits = grads->logits;
+    sq_tuning t = tuning ? *tuning : default_tuning();
+    t.chunk = march->ckpt_every;
+    return bwd_checked(p, &io, stats, &t, ws, ws_bytes, stream);
+}
+
+// ---- batched -------------------------------------------------------------------
+size_t sq_batch_workspace(const sq_batch* b) {
+    Plan p;
+    if (make_plan(b, 4, p)) return 0;
+    return sqr::batch_workspace_bytes(p.g, p.d);
+}
+
+sq_status sq_batch_build_index(const sq_batch* b, const sq_batch_io* io, void* ws, size_t ws_bytes,
+                               hipStream_t stream) {
+    Plan p;
+    sq_status s;
+    if ((s = make_plan(b, 8, p))) return s;
+    return index_checked(p, io, ws, ws_bytes, stream);
+}
+
+sq_status sq_batch_render_fwd(const sq_batch* b, const sq_batch_io* io, int64_t* stats, const sq_tuning* tuning,
+                              void* ws, size_t ws_bytes, hipStream_t stream) {
+    sqr::TuneDev tune;
+    sq_status s;
+    if ((s = tuning_of(tuning, tune))) return s;
+    Plan p;
+    if ((s = make_plan(b, tune.tile_w, p))) return s;
+    return fwd_checked(p, io, stats, tuning, ws, ws_bytes, stream);
+}
+
+sq_status sq_batch_render_bwd(const sq_batch* b, const sq_batch_io* io, int64_t* stats, const sq_tuning* tuning,
+                              void* ws, size_t ws_bytes, hipStream_t stream) {
+    sqr::TuneDev tune;
+    sq_status s;
+    if ((s = tuning_of(tuning, tune))) return s;
+    Plan p;
+    if ((s = make_plan(b, tune.tile_w, p))) return s;
+    return bwd_checked(p, io, stats, tuning, ws, ws_bytes, stream);
+}
+
+sq_status sq_batch_step(const sq_batch* b, const sq_batch_io* io, const sq_tuning* tuning, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    // validate all three stages before launching the first
+    {
+        sqr::TuneDev tune;
+        if ((s = tuning_of(tuning, tune))) return s;
+        Plan p;
+        if ((s = make_plan(b, tune.tile_w, p))) return s;
+        if ((s = check_io_render(p, io))) return s;
+        if (!io->totals || !io->depth || !io->sem || !io->t_final || !io->ckpt || !io->g_means || !io->g_quats ||
+            !io->g_scales || !io->g_eps || !io->g_opacity || !io->g_logits)
+            return fail(SQ_ERR_INVALID, "a step needs totals, forward outputs, ckpt and gradient outputs");
+        const int K = chunk_of(tuning, p.m);
+        if (!(K == 4 || K == 8 || K == 16)) return fail(SQ_ERR_INVALID, "step needs a chunk in {4, 8, 16}");
+        if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
+            !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
+            return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply");
+        if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+    }
+    if ((s = sq_batch_build_index(b, io, ws, ws_bytes, stream))) return s;
+    if ((s = sq_batch_render_fwd(b, io, nullptr, tuning, ws, ws_bytes, stream))) return s;
+    return sq_batch_render_bwd(b, io, nullptr, tuning, ws, ws_bytes, stream);
+}
+
+sq_status sq_batch_step_graph_create(const sq_batch* b, const sq_batch_io* io, const sq_tuning* tuning, void* ws,
+                                     size_t ws_bytes, hipStream_t stream, sq_graph* out) {
+    if (!out) return fail(SQ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!stream) return fail(SQ_ERR_INVALID, "graph capture needs a non-default stream");
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_status(e, "hipStreamBeginCapture");
+    const sq_status st = sq_batch_step(b, io, tuning, ws, ws_bytes, stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(stream, &graph);
+    if (st != SQ_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return hip_status(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_status(e, "hipGraphInstantiate");
+    }
+    GraphImpl* g = new (std::nothrow) GraphImpl{graph, exec};
+    if (!g) {
+        hipGraphExecDestroy(exec);
+        hipGraphDestroy(graph);
+        return fail(SQ_ERR_HIP, "out of host memory");
+    }
+    *out = reinterpret_cast<sq_graph>(g);
+    return ok();
+}
+
+sq_status sq_graph_launch(sq_graph graph, hipStream_t stream) {
+    if (!graph) return fail(SQ_ERR_INVALID, "graph is NULL");
+    GraphImpl* g = reinterpret_cast<GraphImpl*>(graph);
+    return hip_status(hipGraphLaunch(g->exec, stream), "hipGraphLaunch");
+}
+
+sq_status sq_graph_destroy(sq_graph graph) {
+    if (!graph) return ok();
+    GraphImpl* g = reinterpret_cast<GraphImpl*>(graph);
+    hipGraphExecDestroy(g->exec);
+    hipGraphDestroy(g->graph);
+    delete g;
+    return ok();
+}
+
+sq_status sq_batch_autotune(const sq_batch* b, const sq_batch_io* io, const sq_tuning* candidates,
+                            int32_t n_candidates, int32_t reps, int32_t* best_index, float* ms_per_candidate,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!candidates || n_candidates < 1 || reps < 1 || !best_index)
+        return fail(SQ_ERR_INVALID, "need candidates, n_candidates >= 1, reps >= 1 and best_index");
+    // validate every candidate first: an invalid one rejects the call before any launch
+    for (int i = 0; i < n_candidates; ++i) {
+        sqr::TuneDev tune;
+        sq_status s;
+        if ((s = tuning_of(&candidates[i], tune))) return s;
+        Plan p;
+        if ((s = make_plan(b, tune.tile_w, p))) return s;
+        if ((s = check_io_render(p, io))) return s;
+        if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+        const int K = chunk_of(&candidates[i], p.m);
+        if (!(K == 4 || K == 8 || K == 16)) return fail(SQ_ERR_INVALID, "candidate %d: chunk %d", i, K);
+        if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
+            !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
+            return fail(SQ_ERR_UNSUPPORTED, "candidate %d: primitive-major backward does not apply", i);
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(SQ_ERR_HIP, "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(SQ_ERR_HIP, "hipEventCreate");
+    }
+    float best = 0.0f;
+    int bi = -1;
+    sq_status st = SQ_OK;
+    for (int i = 0; i < n_candidates && st == SQ_OK; ++i) {
+        st = sq_batch_step(b, io, &candidates[i], ws, ws_bytes, stream);   // warm-up
+        if (st) break;
+        hipEventRecord(e0, stream);
+        for (int r = 0; r < reps && st == SQ_OK; ++r) st = sq_batch_step(b, io, &candidates[i], ws, ws_bytes, stream);
+        hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            st = fail(SQ_ERR_HIP, "hipEventSynchronize");
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (ms_per_candidate) ms_per_candidate[i] = ms;
+        if (bi < 0 || ms < best) {
+            best = ms;
+            bi = i;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    *best_index = bi;
+    return ok();
 }
 
 }  // extern "C"

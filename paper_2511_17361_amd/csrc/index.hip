@@ -16,6 +16,7 @@
 //   k_scan_*        exclusive prefix sum V_f = scan(V_n) and E = sum(V_n).
 #include "sqr_device.h"
 #include "sqr_internal.h"
+#include "sqr_launch.h"
 
 namespace sqr {
 
@@ -44,13 +45,24 @@ struct TileShape {
 };
 
 template <bool WRITE>
-__global__ __launch_bounds__(TILE_THREADS) void k_tile_lists(const int4* __restrict__ boxes, int n, GridDev g,
-                                                              TileShape ts, int32_t* __restrict__ counts,
-                                                              const int32_t* __restrict__ offsets,
-                                                              int32_t* __restrict__ ids, int64_t capacity) {
+__global__ __launch_bounds__(TILE_THREADS) void k_tile_lists(const BatchDesc* __restrict__ desc,
+                                                              const int4* __restrict__ boxes_all, GridDev g,
+                                                              TileShape ts, int32_t* __restrict__ counts_all,
+                                                              const int32_t* __restrict__ offsets_all,
+                                                              int32_t* __restrict__ ids_all) {
     __shared__ int4 cand[CAND_CAP];
     __shared__ int wave_cnt[TILE_THREADS / 64];
     __shared__ int batch_n;
+
+    const int scene = blockIdx.y;
+    const SceneDev& S = desc->s[scene];
+    const int n = S.n;
+    const int4* boxes = boxes_all + S.prim_off;
+    const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
+    int32_t* counts = counts_all + (int64_t)scene * nvox;
+    const int32_t* offsets = WRITE ? offsets_all + (int64_t)scene * nvox : nullptr;
+    int32_t* ids = WRITE ? ids_all + S.ids_base : nullptr;
+    const int64_t capacity = S.cap;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -74,7 +86,7 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile_lists(const int4* __restr
     __syncthreads();
     for (int base = 0; base < n; base += TILE_THREADS) {
         const int k = base + tid;
-        int4 b = make_int4(1, 1, 1, 0);
+        int4 b = make_int4(EMPTY_BOX, EMPTY_BOX, EMPTY_BOX, 0);
         if (k < n) b = boxes[k];
         const bool keep = (k < n) && box_overlaps(b.x, x0, x1) && box_overlaps(b.y, y0, y1) &&
                           box_overlaps(b.z, z0, z1);
@@ -117,7 +129,8 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile_lists(const int4* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan over the voxel counts (three passes over 2048-element blocks).
+// Exclusive scan over the voxel counts of each scene (three passes over
+// 2048-element blocks; blockIdx.y = scene).
 // ---------------------------------------------------------------------------
 constexpr int SCAN_BLOCK = 256;
 constexpr int SCAN_PER_THREAD = 8;
@@ -140,21 +153,23 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t val, int64_t* sh
     return incl - val;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(const int32_t* __restrict__ counts, int64_t nvox,
-                                                              int64_t* __restrict__ partials) {
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(const int32_t* __restrict__ counts_all, int64_t nvox,
+                                                              int nparts, int64_t* __restrict__ partials_all) {
     __shared__ int64_t sh[SCAN_BLOCK];
+    const int32_t* counts = counts_all + (int64_t)blockIdx.y * nvox;
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
     int64_t s = 0;
     for (int i = 0; i < SCAN_PER_THREAD; ++i)
         if (base + i < nvox) s += counts[base + i];
     int64_t tot;
     block_exclusive_scan(s, sh, tot);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (threadIdx.x == 0) partials_all[(int64_t)blockIdx.y * nparts + blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int64_t* __restrict__ partials, int nparts,
-                                                         int64_t* __restrict__ total_out) {
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int64_t* __restrict__ partials_all, int nparts,
+                                                         int64_t* __restrict__ totals) {
     __shared__ int64_t sh[SCAN_BLOCK];
+    int64_t* partials = partials_all + (int64_t)blockIdx.x * nparts;
     int64_t carry = 0;
     for (int base = 0; base < nparts; base += SCAN_BLOCK) {
         const int i = base + threadIdx.x;
@@ -164,13 +179,15 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int64_t* __restrict__ p
         if (i < nparts) partials[i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) *total_out = carry;
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __restrict__ counts, int64_t nvox,
-                                                           const int64_t* __restrict__ part_off,
-                                                           int32_t* __restrict__ offsets) {
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __restrict__ counts_all, int64_t nvox,
+                                                           int nparts, const int64_t* __restrict__ part_off_all,
+                                                           int32_t* __restrict__ offsets_all) {
     __shared__ int64_t sh[SCAN_BLOCK];
+    const int32_t* counts = counts_all + (int64_t)blockIdx.y * nvox;
+    int32_t* offsets = offsets_all + (int64_t)blockIdx.y * nvox;
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
     int32_t c[SCAN_PER_THREAD];
     int64_t s = 0;
@@ -179,7 +196,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __rest
         s += c[i];
     }
     int64_t tot;
-    int64_t run = block_exclusive_scan(s, sh, tot) + part_off[blockIdx.x];
+    int64_t run = block_exclusive_scan(s, sh, tot) + part_off_all[(int64_t)blockIdx.y * nparts + blockIdx.x];
     for (int i = 0; i < SCAN_PER_THREAD; ++i) {
         if (base + i < nvox) offsets[base + i] = (int32_t)run;
         run += c[i];
@@ -204,32 +221,30 @@ static TileShape pick_tile(const GridDev& g) {
     return ts;
 }
 
-size_t index_workspace_bytes(int64_t nvox, int n) {
-    const int64_t nparts = (nvox + SCAN_TILE - 1) / SCAN_TILE;
-    return align_up((size_t)n * sizeof(int4)) + align_up((size_t)(nparts + 1) * sizeof(int64_t));
+int scan_parts(const GridDev& g) {
+    const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
+    return (int)((nvox + SCAN_TILE - 1) / SCAN_TILE);
 }
 
-hipError_t launch_build_index(const GridDev& g, const float* means, int n, int32_t* counts, int32_t* offsets,
-                              int32_t* ids, int64_t capacity, int64_t* total, void* ws, hipStream_t st) {
+void launch_index_kernels(const GridDev& g, const BatchDesc& d, const BatchDesc* desc_dev, const BatchIO& io,
+                          int4* boxes, int64_t* partials, hipStream_t st) {
     const int64_t nvox = (int64_t)g.X * g.Y * g.Z;
-    const int64_t nparts = (nvox + SCAN_TILE - 1) / SCAN_TILE;
-    char* p = (char*)ws;
-    int4* boxes = (int4*)p;
-    p += align_up((size_t)n * sizeof(int4));
-    int64_t* partials = (int64_t*)p;
-
-    if (n > 0) hipLaunchKernelGGL(k_prep_boxes, dim3((n + 255) / 256), dim3(256), 0, st, means, n, g, boxes);
+    const int np = scan_parts(g);
+    const int S = d.n_scenes;
+    if (d.total_prims > 0)
+        hipLaunchKernelGGL(k_prep_boxes, dim3((d.total_prims + 255) / 256), dim3(256), 0, st, io.means,
+                           d.total_prims, g, boxes);
     const TileShape ts = pick_tile(g);
     const int ntiles = ts.ntx * ts.nty * ts.ntz;
-    hipLaunchKernelGGL(k_tile_lists<false>, dim3(ntiles), dim3(TILE_THREADS), 0, st, boxes, n, g, ts, counts,
-                       (const int32_t*)nullptr, (int32_t*)nullptr, capacity);
-    hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)nparts), dim3(SCAN_BLOCK), 0, st, counts, nvox, partials);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, st, partials, (int)nparts, total);
-    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nparts), dim3(SCAN_BLOCK), 0, st, counts, nvox,
-                       (const int64_t*)partials, offsets);
-    hipLaunchKernelGGL(k_tile_lists<true>, dim3(ntiles), dim3(TILE_THREADS), 0, st, boxes, n, g, ts, counts,
-                       (const int32_t*)offsets, ids, capacity);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_tile_lists<false>, dim3(ntiles, S), dim3(TILE_THREADS), 0, st, desc_dev,
+                       (const int4*)boxes, g, ts, io.counts, (const int32_t*)nullptr, (int32_t*)nullptr);
+    hipLaunchKernelGGL(k_scan_partials, dim3(np, S), dim3(SCAN_BLOCK), 0, st, (const int32_t*)io.counts, nvox, np,
+                       partials);
+    hipLaunchKernelGGL(k_scan_top, dim3(S), dim3(SCAN_BLOCK), 0, st, partials, np, io.totals);
+    hipLaunchKernelGGL(k_scan_final, dim3(np, S), dim3(SCAN_BLOCK), 0, st, (const int32_t*)io.counts, nvox, np,
+                       (const int64_t*)partials, io.offsets);
+    hipLaunchKernelGGL(k_tile_lists<true>, dim3(ntiles, S), dim3(TILE_THREADS), 0, st, desc_dev,
+                       (const int4*)boxes, g, ts, io.counts, (const int32_t*)io.offsets, io.ids);
 }
 
 }  // namespace sqr

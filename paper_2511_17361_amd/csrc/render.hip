@@ -1,34 +1,37 @@
 // Forward and backward ray march of the superquadric renderer (gfx950).
 //
 // Mapping: one wavefront = one tile of 64 rays (tile_w x 64/tile_w pixels of
-// one camera).  Rays of a tile are nearly parallel, so at a given sample index
-// most lanes sit in the same voxel.  Per sample the wave walks the distinct
-// voxels of its active lanes one at a time; inside one voxel the primitive id,
-// its prepared record and its logits are wave-uniform and arrive through the
-// scalar data cache, and each lane evaluates p_o at its own sample point.
-// Nothing here is a dense contraction, so there is no MFMA use.
+// one camera of one scene).  Rays of a tile are nearly parallel, so at a given
+// sample index most lanes sit in the same voxel.  Per sample the wave walks the
+// distinct voxels of its active lanes one at a time; inside one voxel the
+// primitive id, its prepared record and its logits are wave-uniform and arrive
+// through the scalar data cache, and each lane evaluates p_o at its own sample
+// point.  Nothing here is a dense contraction, so there is no MFMA use.
+//
+// Tiles of all scenes of a batch form one global tile order.  Waves take tiles
+// either from a static grid (one wave per tile, XCD-grouped block order) or,
+// persistently, from eight per-XCD work queues (each XCD drains a contiguous
+// range of the tile order first, then steals from the others); either way
+// every wave exits once the tile order is exhausted.
 //
 // Forward (Sec. 3.3 "Forward Pass", Eq. eq:alpha_sem_sq, eq:alpha_composite,
 // eq:depth_sem).  Backward (Sec. 3.3 "Backward Pass"): per ray, chunks of K
 // samples are replayed back to front from the transmittance checkpoints the
-// forward wrote.  Pass 1 recomputes a_j, alpha_j, T_j and
-// G_j = g_D t_j + <g_S, s_j> front to back inside the chunk (kept in LDS);
-// pass 2 walks the chunk back to front carrying
-// Q_j = alpha_j G_j + (1 - alpha_j) Q_{j+1}, so dL/dalpha_j = T_j (G_j - Q_{j+1})
-// needs no division by (1 - alpha) and no per-sample state outside the chunk.
-// Each pair's parameter contributions are summed across the wave by a
-// transposing butterfly and land in the per-primitive accumulator with one
-// lane-parallel float atomic per pair.
+// forward wrote; Q_j = alpha_j G_j + (1 - alpha_j) Q_{j+1} gives
+// dL/dalpha_j = T_j (G_j - Q_{j+1}) without dividing by (1 - alpha) and
+// without per-sample state outside the chunk.
 #include "sqr_device.h"
 #include "sqr_internal.h"
+#include "sqr_launch.h"
 
 #include <algorithm>
 
 namespace sqr {
 
-// accumulator row layout (floats per primitive = ACC_ROW(CP))
+// accumulator row layout (floats per primitive = AccRow<CP>::P)
 constexpr int A_SIG = 0, A_E1 = 1, A_E2 = 2, A_XS = 3, A_R = 6, A_LG = 15;
 template <int CP> struct AccRow { static constexpr int V = A_LG + CP; static constexpr int P = V <= 32 ? 32 : 64; };
+template <int VP> struct Log2 { static constexpr int v = VP == 64 ? 6 : VP == 32 ? 5 : VP == 16 ? 4 : 0; };
 
 int padded_classes(int C) {
     if (C <= 4) return 4;
@@ -36,36 +39,59 @@ int padded_classes(int C) {
     if (C <= 17) return 17;
     return 32;
 }
-static int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
+int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
 
 // Occupancy targets (waves per SIMD) that the register allocator must meet.
-#define FWD_WPE(CP) ((CP) <= 8 ? 6 : (CP) <= 17 ? 5 : 3)
+#define FWD_WPE(CP) ((CP) <= 8 ? 6 : (CP) <= 17 ? 4 : 3)
 #define BWD_WPE(CP, KC) ((KC) == 4 && (CP) <= 17 ? 4 : 3)
 
+// Kernel parameters shared by every render kernel.
+struct Ctx {
+    GridDev g;
+    MarchDev mr;
+    int C;
+    int total_tiles;
+    const BatchDesc* desc;      // device copy (workspace)
+    int* queue;                 // per-XCD work counters of this launch
+    const int32_t *counts, *offsets, *ids;
+    const float *rec, *lgp;
+    const float *origins, *dirs;
+    float *depth, *sem, *probs, *t_final, *ckpt;
+    const float *g_depth, *g_sem;
+    float* acc;
+    int64_t* stats;
+    int bitmap_words;           // per-wave bitmap size of the primitive-major backward
+};
+
 // ---------------------------------------------------------------------------
-// Per-primitive preparation
+// Per-primitive preparation (all primitives of the batch)
 // ---------------------------------------------------------------------------
 template <int CP>
-__global__ __launch_bounds__(256) void k_prep_records(PrimsDev pr, GridDev g, float* __restrict__ rec,
-                                                      float* __restrict__ lgp) {
+__global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const float* __restrict__ means,
+                                                      const float* __restrict__ quats,
+                                                      const float* __restrict__ scales,
+                                                      const float* __restrict__ eps,
+                                                      const float* __restrict__ opacity,
+                                                      const float* __restrict__ logits, GridDev g,
+                                                      float* __restrict__ rec, float* __restrict__ lgp) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= pr.n) return;
-    float qw = pr.quats[4 * k + 0], qx = pr.quats[4 * k + 1], qy = pr.quats[4 * k + 2], qz = pr.quats[4 * k + 3];
+    if (k >= n_total) return;
+    float qw = quats[4 * k + 0], qx = quats[4 * k + 1], qy = quats[4 * k + 2], qz = quats[4 * k + 3];
     const float qinv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
     qw *= qinv; qx *= qinv; qy *= qinv; qz *= qinv;
     const float R[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
                         2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
                         2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
-    const float is[3] = {1.0f / pr.scales[3 * k], 1.0f / pr.scales[3 * k + 1], 1.0f / pr.scales[3 * k + 2]};
-    const float e1 = pr.eps[2 * k], e2 = pr.eps[2 * k + 1];
+    const float is[3] = {1.0f / scales[3 * k], 1.0f / scales[3 * k + 1], 1.0f / scales[3 * k + 2]};
+    const float e1 = eps[2 * k], e2 = eps[2 * k + 1];
     float* r = rec + (size_t)k * REC;
-    r[0] = pr.means[3 * k]; r[1] = pr.means[3 * k + 1]; r[2] = pr.means[3 * k + 2];
+    r[0] = means[3 * k]; r[1] = means[3 * k + 1]; r[2] = means[3 * k + 2];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) r[3 + 3 * i + j] = R[3 * i + j] * is[i];
     r[12] = 2.0f / e2;
     r[13] = 2.0f / e1;
     r[14] = e2 / e1;
-    r[15] = pr.opacity[k];
+    r[15] = opacity[k];
     // f >= max(|u|,|v|,|w|)^(2/eps1): culled where that bound reaches F_CULL
     r[16] = exp2f(0.5f * e1 * log2f(F_CULL));
     r[17] = is[0]; r[18] = is[1]; r[19] = is[2];
@@ -73,7 +99,7 @@ __global__ __launch_bounds__(256) void k_prep_records(PrimsDev pr, GridDev g, fl
     prim_box(g, r[0], r[1], r[2], box);
     r[20] = __int_as_float(box[0]); r[21] = __int_as_float(box[1]); r[22] = __int_as_float(box[2]);
     r[23] = 0.0f;
-    for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < pr.C ? pr.logits[(size_t)k * pr.C + c] : 0.0f;
+    for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < C ? logits[(size_t)k * C + c] : 0.0f;
 }
 
 __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, float v) {
@@ -81,84 +107,150 @@ __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, 
         p[i] = v;
 }
 
+__global__ __launch_bounds__(64) void k_fill_int(int* __restrict__ p, int n, int v) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+__global__ __launch_bounds__(64) void k_put_desc(BatchDesc d, BatchDesc* __restrict__ dst) {
+    const int* src = reinterpret_cast<const int*>(&d);
+    int* out = reinterpret_cast<int*>(dst);
+    constexpr int nw = (int)(sizeof(BatchDesc) / sizeof(int));
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) out[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
-// Tile geometry
+// Tile scheduling and lane setup
 // ---------------------------------------------------------------------------
-struct TileMap {
-    int tile_w, tile_h, tiles_x, tiles_y, n_tiles;
-};
+template <bool PERSIST, typename F>
+__device__ __forceinline__ void for_each_tile(const Ctx& P, F&& body) {
+    const int wpb = blockDim.x >> 6;
+    const int total = P.total_tiles;
+    if (!PERSIST) {
+        // wave-uniform by construction; readfirstlane tells the compiler so, which
+        // keeps everything derived from the tile (scene, pointers) in SGPRs
+        const int t = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6));
+        if (t < total) body(t);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int xcd = blockIdx.x & (N_XCD - 1);
+    const int per = (total + N_XCD - 1) / N_XCD;
+    for (int q = 0; q < N_XCD; ++q) {
+        const int x = (xcd + q) & (N_XCD - 1);
+        const int lo = x * per, hi = min(total, lo + per);
+        if (lo >= hi) continue;
+        while (true) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(&P.queue[x * QUEUE_STRIDE], 1);
+            t = __builtin_amdgcn_readlane(t, 0);
+            if (lo + t >= hi) break;
+            body(lo + t);
+        }
+    }
+}
+
+__device__ __forceinline__ int find_scene(const BatchDesc* d, int tile) {
+    const int ns = d->n_scenes;
+    int s = 0;
+    for (int i = 1; i < ns; ++i) s += (tile >= d->s[i].tile_off) ? 1 : 0;
+    return s;
+}
 
 struct RayLane {
     bool valid;
     int cam, px, py;
-    int64_t ray, pix;
     float ox, oy, oz, dx, dy, dz;
 };
 
-__device__ __forceinline__ bool map_tile(const TileMap& tm, const RaysDev& rays, RayLane& rl) {
+// pixel index inside the camera image, ray index inside the scene, global ray index
+__device__ __forceinline__ int64_t lane_pix(const RayLane& rl, const SceneDev& S) {
+    return (int64_t)rl.py * S.W + rl.px;
+}
+__device__ __forceinline__ int64_t lane_lray(const RayLane& rl, const SceneDev& S) {
+    return ((int64_t)rl.cam * S.H + rl.py) * S.W + rl.px;
+}
+__device__ __forceinline__ int64_t lane_ray(const RayLane& rl, const SceneDev& S) {
+    return S.ray_off + lane_lray(rl, S);
+}
+
+__device__ __forceinline__ RayLane setup_lane(const Ctx& P, const SceneDev& S, int tile) {
+    RayLane rl;
     const int lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile = blk * wpb + (threadIdx.x >> 6);
-    if (tile >= tm.n_tiles) return false;
-    const int tpc = tm.tiles_x * tm.tiles_y;
+    const int tw = P.desc->tile_w, th = P.desc->tile_h;
+    const int tpc = S.tiles_x * S.tiles_y;
     rl.cam = tile / tpc;
     const int rem = tile - rl.cam * tpc;
-    const int ty = rem / tm.tiles_x, tx = rem - ty * tm.tiles_x;
-    rl.px = tx * tm.tile_w + (lane % tm.tile_w);
-    rl.py = ty * tm.tile_h + (lane / tm.tile_w);
-    rl.valid = (rl.px < rays.W) & (rl.py < rays.H);
-    rl.pix = (int64_t)rl.py * rays.W + rl.px;
-    rl.ray = (int64_t)rl.cam * rays.H * rays.W + rl.pix;
+    const int ty = rem / S.tiles_x, tx = rem - ty * S.tiles_x;
+    rl.px = tx * tw + (lane % tw);
+    rl.py = ty * th + (lane / tw);
+    rl.valid = (rl.px < S.W) & (rl.py < S.H);
     rl.ox = rl.oy = rl.oz = rl.dx = rl.dy = rl.dz = 0.0f;
     if (rl.valid) {
-        const float* o = rays.origins + 3 * rl.ray;
-        const float* d = rays.dirs + 3 * rl.ray;
+        const int64_t ray = lane_ray(rl, S);
+        const float* o = P.origins + 3 * ray;
+        const float* d = P.dirs + 3 * ray;
         rl.ox = o[0]; rl.oy = o[1]; rl.oz = o[2];
         rl.dx = d[0]; rl.dy = d[1]; rl.dz = d[2];
     }
-    return true;
+    return rl;
 }
 
-struct FwdParams {
-    GridDev g;
-    IndexDev idx;
-    int N, C;
-    const float* rec;
-    const float* lgp;
-    RaysDev rays;
-    MarchDev mr;
-    TileMap tm;
-    float *depth, *sem, *probs, *t_final, *ckpt;
-    int64_t* stats;
+// Index view of one scene.
+struct SceneIndex {
+    const int32_t* counts;
+    const int32_t* offsets;
+    ci_ptr ids;
+    int64_t cap;
+    cf_ptr rec;     // records of the scene's primitives (local id k at rec + k*REC)
+    cf_ptr lgp;
+    int n;
 };
+
+template <int CP>
+__device__ __forceinline__ SceneIndex scene_index(const Ctx& P, int s, const SceneDev& S) {
+    SceneIndex x;
+    const int64_t nvox = (int64_t)P.g.X * P.g.Y * P.g.Z;
+    x.counts = P.counts + (int64_t)s * nvox;
+    x.offsets = P.offsets + (int64_t)s * nvox;
+    x.ids = as_const(P.ids) + S.ids_base;
+    x.cap = S.cap;
+    x.rec = as_const(P.rec) + (size_t)S.prim_off * REC;
+    x.lgp = as_const(P.lgp) + (size_t)S.prim_off * CP;
+    x.n = S.n;
+    return x;
+}
+
+// Uniform list length of voxel list (f0, n0), clamped to the scene's capacity.
+__device__ __forceinline__ int clamp_list(int f0, int n0, int64_t cap) {
+    if (f0 < 0) return 0;
+    if ((int64_t)f0 + n0 > cap) return (int)max((int64_t)0, cap - f0);
+    return n0;
+}
 
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
 template <int CP, bool CKPT, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP), 8))) void k_render_fwd(FwdParams P) {
-    RayLane rl;
-    if (!map_tile(P.tm, P.rays, rl)) return;    // whole wavefront
-    const int64_t R = (int64_t)P.rays.n_cams * P.rays.H * P.rays.W;
-    const int32_t* __restrict__ counts = P.idx.counts;
-    const int32_t* __restrict__ offsets = P.idx.offsets;
-    const ci_ptr ids = as_const(P.idx.ids);
-    const cf_ptr rec = as_const(P.rec);
-    const cf_ptr lgp = as_const(P.lgp);
+__device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile) {
+    const SceneDev& S = P.desc->s[s];
+    const RayLane rl = setup_lane(P, S, tile);
+    const SceneIndex X = scene_index<CP>(P, s, S);
     const int L = P.mr.L, K = P.mr.K;
+    const int64_t R = (int64_t)S.cams * S.H * S.W;
+    const int nck = CKPT ? (L + K - 1) / K : 0;
+    float* ckpt = CKPT ? P.ckpt + (int64_t)nck * S.ray_off : nullptr;
 
     float T = rl.valid ? 1.0f : 0.0f;
     float D = 0.0f;
-    float S[CP];
+    float Sv[CP];
 #pragma unroll
-    for (int c = 0; c < CP; ++c) S[c] = 0.0f;
+    for (int c = 0; c < CP; ++c) Sv[c] = 0.0f;
     bool alive = rl.valid;
     int64_t st_samples = 0, st_pairs = 0, st_nz = 0;
 
     SamplePos nxt = pinned_sample(P.g, P.mr.t_near, P.mr.delta, 0, rl.ox, rl.oy, rl.oz, rl.dx, rl.dy, rl.dz);
     int n_nxt = 0, f_nxt = 0;
-    if (alive && nxt.v >= 0) { n_nxt = counts[nxt.v]; f_nxt = offsets[nxt.v]; }
+    if (alive && nxt.v >= 0) { n_nxt = X.counts[nxt.v]; f_nxt = X.offsets[nxt.v]; }
 
     for (int j = 0; j < L; ++j) {
         const SamplePos cur = nxt;
@@ -166,16 +258,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP)
         if (j + 1 < L) {
             nxt = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j + 1, rl.ox, rl.oy, rl.oz, rl.dx, rl.dy, rl.dz);
             n_nxt = 0; f_nxt = 0;
-            if (alive && nxt.v >= 0) { n_nxt = counts[nxt.v]; f_nxt = offsets[nxt.v]; }
+            if (alive && nxt.v >= 0) { n_nxt = X.counts[nxt.v]; f_nxt = X.offsets[nxt.v]; }
         }
-        if (CKPT && (j % K) == 0 && rl.valid) P.ckpt[(int64_t)(j / K) * R + rl.ray] = T;
+        if (CKPT && (j % K) == 0 && rl.valid) ckpt[(int64_t)(j / K) * R + lane_lray(rl, S)] = T;
 
         const bool act = alive && (cur.v >= 0) && (n > 0);
         if (wave_ballot(act) != 0) {
             float a = 0.0f;
-            float s[CP];
+            float sv[CP];
 #pragma unroll
-            for (int c = 0; c < CP; ++c) s[c] = 0.0f;
+            for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
             if (STATS && act) { ++st_samples; st_pairs += n; }
             bool pend = act;
             uint64_t m;
@@ -183,21 +275,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP)
                 const int leader = __builtin_ctzll(m);
                 const int v0 = readlane_i(cur.v, leader);
                 const int f0 = readlane_i(f, leader);
-                int n0 = readlane_i(n, leader);
-                if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity) n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                const int n0 = clamp_list(f0, readlane_i(n, leader), X.cap);
                 const bool mine = pend && (cur.v == v0);
                 if (mine) {
                     for (int e = 0; e < n0; ++e) {
-                        const int k = ids[f0 + e];
-                        if ((unsigned)k >= (unsigned)P.N) continue;
-                        const cf_ptr r = rec + (size_t)k * REC;
+                        const int k = X.ids[f0 + e];
+                        if ((unsigned)k >= (unsigned)X.n) continue;
+                        const cf_ptr r = X.rec + (size_t)k * REC;
                         const float p = eval_p(r, cur.x, cur.y, cur.z);
                         if (STATS && pair_kept(r, cur.x, cur.y, cur.z)) ++st_nz;
                         if (p != 0.0f) {
                             a = fmaf(p, r[15], a);
-                            const cf_ptr lg = lgp + (size_t)k * CP;
+                            const cf_ptr lg = X.lgp + (size_t)k * CP;
 #pragma unroll
-                            for (int c = 0; c < CP; ++c) s[c] = fmaf(p, lg[c], s[c]);
+                            for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
                         }
                     }
                 }
@@ -208,40 +299,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP)
             const float w = T * alpha;
             D = fmaf(w, cur.t, D);
 #pragma unroll
-            for (int c = 0; c < CP; ++c) S[c] = fmaf(w, s[c], S[c]);
+            for (int c = 0; c < CP; ++c) Sv[c] = fmaf(w, sv[c], Sv[c]);
             T = T * (1.0f - alpha);
             alive = alive && (T > 0.0f);
         }
         if (wave_ballot(alive) == 0) {
             // every later sample of this tile is exactly zero
             if (CKPT && rl.valid)
-                for (int c = j / K + 1; c * K < L; ++c) P.ckpt[(int64_t)c * R + rl.ray] = T;
+                for (int c = j / K + 1; c * K < L; ++c) ckpt[(int64_t)c * R + lane_lray(rl, S)] = T;
             break;
         }
     }
 
     if (rl.valid) {
-        P.depth[rl.ray] = D;
-        P.t_final[rl.ray] = T;
-        const int64_t HW = (int64_t)P.rays.H * P.rays.W;
-        float* semp = P.sem + (int64_t)rl.cam * P.C * HW + rl.pix;
+        const int64_t ray = lane_ray(rl, S);
+        P.depth[ray] = D;
+        P.t_final[ray] = T;
+        const int64_t HW = (int64_t)S.H * S.W;
+        const int64_t base = S.ray_off * P.C + (int64_t)rl.cam * P.C * HW + lane_pix(rl, S);
+        float* semp = P.sem + base;
 #pragma unroll
         for (int c = 0; c < CP; ++c)
-            if (c < P.C) semp[c * HW] = S[c];
+            if (c < P.C) semp[c * HW] = Sv[c];
         if (P.probs) {
-            float mx = S[0];
+            float mx = Sv[0];
 #pragma unroll
             for (int c = 1; c < CP; ++c)
-                if (c < P.C) mx = fmaxf(mx, S[c]);
+                if (c < P.C) mx = fmaxf(mx, Sv[c]);
             float e[CP];
             float sum = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) {
-                e[c] = c < P.C ? expf(S[c] - mx) : 0.0f;
+                e[c] = c < P.C ? expf(Sv[c] - mx) : 0.0f;
                 sum += e[c];
             }
             const float inv = 1.0f / sum;
-            float* pp = P.probs + (int64_t)rl.cam * P.C * HW + rl.pix;
+            float* pp = P.probs + base;
 #pragma unroll
             for (int c = 0; c < CP; ++c)
                 if (c < P.C) pp[c * HW] = e[c] * inv;
@@ -255,61 +348,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Backward
-// ---------------------------------------------------------------------------
-struct BwdParams {
-    GridDev g;
-    IndexDev idx;
-    int N, C;
-    const float* rec;
-    const float* lgp;
-    RaysDev rays;
-    MarchDev mr;
-    TileMap tm;
-    const float *ckpt, *g_depth, *g_sem;
-    float* acc;
-    int64_t* stats;
-    int bitmap_words;   // per-wave bitmap size of the primitive-major path
-};
+template <int CP, bool CKPT, bool STATS, bool PERSIST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP), 8))) void k_render_fwd(Ctx P) {
+    for_each_tile<PERSIST>(P, [&](int t) {
+        const int s = find_scene(P.desc, t);
+        fwd_tile<CP, CKPT, STATS>(P, s, t - P.desc->s[s].tile_off);
+    });
+}
 
-template <int VP> struct Log2 { static constexpr int v = VP == 64 ? 6 : VP == 32 ? 5 : VP == 16 ? 4 : 0; };
-
+// ---------------------------------------------------------------------------
+// Backward, sample-major (fallback): one reduction per (sample, primitive)
+// ---------------------------------------------------------------------------
 template <int CP, bool STATS>
-__global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
-    extern __shared__ float smem[];   // [wave][4][K][64]
-    RayLane rl;
-    if (!map_tile(P.tm, P.rays, rl)) return;
+__device__ __forceinline__ void bwd_sm_tile(const Ctx& P, int s, int tile, float* sw) {
+    const SceneDev& S = P.desc->s[s];
+    const RayLane rl = setup_lane(P, S, tile);
+    const SceneIndex X = scene_index<CP>(P, s, S);
     constexpr int VP = AccRow<CP>::P;
     constexpr int V = AccRow<CP>::V;
     const int lane = threadIdx.x & 63;
     const int K = P.mr.K, L = P.mr.L;
-    float* sw = smem + (size_t)(threadIdx.x >> 6) * 4 * K * 64;
     float* sm_a = sw;                 // a_j
     float* sm_T = sw + K * 64;        // T_j
     float* sm_G = sw + 2 * K * 64;    // G_j
-    float* sm_v = sw + 3 * K * 64;    // unused slot (keeps the layout 4-wide)
-    (void)sm_v;
-
-    const int64_t R = (int64_t)P.rays.n_cams * P.rays.H * P.rays.W;
-    const int64_t HW = (int64_t)P.rays.H * P.rays.W;
-    const int32_t* __restrict__ counts = P.idx.counts;
-    const int32_t* __restrict__ offsets = P.idx.offsets;
-    const ci_ptr ids = as_const(P.idx.ids);
-    const cf_ptr rec = as_const(P.rec);
-    const cf_ptr lgp = as_const(P.lgp);
-
-    const float gD = (rl.valid && P.g_depth) ? P.g_depth[rl.ray] : 0.0f;
-    float gS[CP];
-#pragma unroll
-    for (int c = 0; c < CP; ++c)
-        gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[((int64_t)rl.cam * P.C + c) * HW + rl.pix] : 0.0f;
-
+    const int64_t R = (int64_t)S.cams * S.H * S.W;
+    const int64_t HW = (int64_t)S.H * S.W;
     const int nck = (L + K - 1) / K;
+    const float* ckpt = P.ckpt + (int64_t)nck * S.ray_off;
+    float* acc = P.acc + (size_t)S.prim_off * VP;
+
+    const float gD = (rl.valid && P.g_depth) ? P.g_depth[lane_ray(rl, S)] : 0.0f;
+    float gS[CP];
+    const int64_t gbase = S.ray_off * P.C + (int64_t)rl.cam * P.C * HW + lane_pix(rl, S);
+#pragma unroll
+    for (int c = 0; c < CP; ++c) gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[gbase + c * HW] : 0.0f;
+
     float Q = 0.0f;
     int64_t st[6] = {0, 0, 0, 0, 0, 0};   // samples, listed, evaluated pairs of pass 1 and of pass 2
     for (int ci = nck - 1; ci >= 0; --ci) {
-        const float Tc = rl.valid ? P.ckpt[(int64_t)ci * R + rl.ray] : 0.0f;
+        const float Tc = rl.valid ? ckpt[(int64_t)ci * R + lane_lray(rl, S)] : 0.0f;
         if (wave_ballot(Tc > 0.0f) == 0) continue;
         const int j0 = ci * K;
         const int jn = min(K, L - j0);
@@ -321,7 +398,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                                                rl.dx, rl.dy, rl.dz);
             int n = 0, f = 0;
             bool act = (T > 0.0f) && (sp.v >= 0);
-            if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+            if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
             if (STATS && act) { st[0] += 1; st[1] += n; }
             float a = 0.0f, G = 0.0f;
             bool pend = act;
@@ -330,19 +407,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                 const int leader = __builtin_ctzll(m);
                 const int v0 = readlane_i(sp.v, leader);
                 const int f0 = readlane_i(f, leader);
-                int n0 = readlane_i(n, leader);
-                if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity) n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                const int n0 = clamp_list(f0, readlane_i(n, leader), X.cap);
                 const bool mine = pend && (sp.v == v0);
                 if (mine) {
                     for (int e = 0; e < n0; ++e) {
-                        const int k = ids[f0 + e];
-                        if ((unsigned)k >= (unsigned)P.N) continue;
-                        const cf_ptr r = rec + (size_t)k * REC;
+                        const int k = X.ids[f0 + e];
+                        if ((unsigned)k >= (unsigned)X.n) continue;
+                        const cf_ptr r = X.rec + (size_t)k * REC;
                         const float p = eval_p(r, sp.x, sp.y, sp.z);
                         if (STATS && pair_kept(r, sp.x, sp.y, sp.z)) st[2] += 1;
                         if (p != 0.0f) {
                             a = fmaf(p, r[15], a);
-                            const cf_ptr lg = lgp + (size_t)k * CP;
+                            const cf_ptr lg = X.lgp + (size_t)k * CP;
                             float gam = 0.0f;
 #pragma unroll
                             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
@@ -376,7 +452,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                                                rl.dx, rl.dy, rl.dz);
             int n = 0, f = 0;
             bool act = live && (sp.v >= 0);
-            if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+            if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
             if (STATS && act) { st[3] += 1; st[4] += n; }
             bool pend = act;
             uint64_t m;
@@ -384,14 +460,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                 const int leader = __builtin_ctzll(m);
                 const int v0 = readlane_i(sp.v, leader);
                 const int f0 = readlane_i(f, leader);
-                int n0 = readlane_i(n, leader);
-                if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity) n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                const int n0 = clamp_list(f0, readlane_i(n, leader), X.cap);
                 const bool mine = pend && (sp.v == v0);
                 for (int e = 0; e < n0; ++e) {
-                    const int k = ids[f0 + e];
-                    if ((unsigned)k >= (unsigned)P.N) continue;
-                    const cf_ptr r = rec + (size_t)k * REC;
-                    const cf_ptr lg = lgp + (size_t)k * CP;
+                    const int k = X.ids[f0 + e];
+                    if ((unsigned)k >= (unsigned)X.n) continue;
+                    const cf_ptr r = X.rec + (size_t)k * REC;
+                    const cf_ptr lg = X.lgp + (size_t)k * CP;
                     float x[VP];
 #pragma unroll
                     for (int i = 0; i < VP; ++i) x[i] = 0.0f;
@@ -439,7 +514,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
                     constexpr int shift = 6 - Log2<VP>::v;
                     const int vi = lane >> shift;
                     if (((lane & ((1 << shift) - 1)) == 0) && vi < V && (vi < A_LG || vi - A_LG < P.C))
-                        atomicAdd(P.acc + (size_t)k * VP + vi, tot);
+                        atomicAdd(acc + (size_t)k * VP + vi, tot);
                 }
                 pend = pend && !mine;
             }
@@ -449,13 +524,23 @@ __global__ __launch_bounds__(256) void k_render_bwd(BwdParams P) {
         for (int i = 0; i < 6; ++i) atomicAdd((unsigned long long*)&P.stats[i], (unsigned long long)st[i]);
 }
 
+template <int CP, bool STATS>
+__global__ __launch_bounds__(256) void k_render_bwd(Ctx P) {
+    extern __shared__ float smem[];   // [wave][3][K][64]
+    float* sw = smem + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 3 * P.mr.K * 64;
+    for_each_tile<false>(P, [&](int t) {
+        const int s = find_scene(P.desc, t);
+        bwd_sm_tile<CP, STATS>(P, s, t - P.desc->s[s].tile_off, sw);
+    });
+}
 
 // ---------------------------------------------------------------------------
 // Backward, primitive-major inside a chunk (default path)
 //
 // Per wavefront and chunk of KC samples:
 //  1. the ids listed in the chunk's voxels are marked in a per-wave LDS bitmap
-//     (one bit per primitive), which enumerates their union in ascending id;
+//     (one bit per primitive of the scene), which enumerates their union in
+//     ascending id;
 //  2. pass 1 walks that union: for each primitive k (wave-uniform, record in
 //     SGPRs) every lane tests which of its KC samples lie in k's box
 //     (= k is listed in the sample's voxel) and accumulates a_j += p sigma_k,
@@ -504,35 +589,32 @@ __device__ __forceinline__ void for_each_marked(const uint32_t* bm, int nw, int 
 }
 
 template <int CP, int KC, bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP, KC), 8))) void k_render_bwd_km(BwdParams P) {
-    extern __shared__ uint32_t bm_all[];
-    RayLane rl;
-    if (!map_tile(P.tm, P.rays, rl)) return;
+__device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint32_t* bm) {
+    const SceneDev& S = P.desc->s[s];
+    const RayLane rl = setup_lane(P, S, tile);
+    const SceneIndex X = scene_index<CP>(P, s, S);
     constexpr int VP = AccRow<CP>::P;
     constexpr int V = AccRow<CP>::V;
     const int lane = threadIdx.x & 63;
-    const int nw = P.bitmap_words;
-    uint32_t* bm = bm_all + (size_t)(threadIdx.x >> 6) * nw;
+    // words of this scene's bitmap (its ids are local, 0 .. n-1)
+    const int nw = ((X.n + 31) / 32 + 63) / 64 * 64;
     const int L = P.mr.L;
-    const int64_t R = (int64_t)P.rays.n_cams * P.rays.H * P.rays.W;
-    const int64_t HW = (int64_t)P.rays.H * P.rays.W;
-    const int32_t* __restrict__ counts = P.idx.counts;
-    const int32_t* __restrict__ offsets = P.idx.offsets;
-    const ci_ptr ids = as_const(P.idx.ids);
-    const cf_ptr rec = as_const(P.rec);
-    const cf_ptr lgp = as_const(P.lgp);
+    const int64_t R = (int64_t)S.cams * S.H * S.W;
+    const int64_t HW = (int64_t)S.H * S.W;
+    const int nck = (L + KC - 1) / KC;
+    const float* ckpt = P.ckpt + (int64_t)nck * S.ray_off;
+    float* acc = P.acc + (size_t)S.prim_off * VP;
 
-    const float gD = (rl.valid && P.g_depth) ? P.g_depth[rl.ray] : 0.0f;
+    const float gD = (rl.valid && P.g_depth) ? P.g_depth[lane_ray(rl, S)] : 0.0f;
     float gS[CP];
+    const int64_t gbase = S.ray_off * P.C + (int64_t)rl.cam * P.C * HW + lane_pix(rl, S);
 #pragma unroll
-    for (int c = 0; c < CP; ++c)
-        gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[((int64_t)rl.cam * P.C + c) * HW + rl.pix] : 0.0f;
+    for (int c = 0; c < CP; ++c) gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[gbase + c * HW] : 0.0f;
 
     int64_t st[6] = {0, 0, 0, 0, 0, 0};
-    const int nck = (L + KC - 1) / KC;
     float Q = 0.0f;
     for (int ci = nck - 1; ci >= 0; --ci) {
-        const float Tc = rl.valid ? P.ckpt[(int64_t)ci * R + rl.ray] : 0.0f;
+        const float Tc = rl.valid ? ckpt[(int64_t)ci * R + lane_lray(rl, S)] : 0.0f;
         if (wave_ballot(Tc > 0.0f) == 0) continue;
         const int j0 = ci * KC;
 
@@ -552,7 +634,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
                 sx[jj] = sp.x; sy[jj] = sp.y; sz[jj] = sp.z;
                 int n = 0, f = 0;
                 bool act = (Tc > 0.0f) && (sp.v >= 0);
-                if (act) { n = counts[sp.v]; f = offsets[sp.v]; act = n > 0; }
+                if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
                 if (act) pv[jj] = pack_voxel(sp.ix, sp.iy, sp.iz);
                 bool pend = act;
                 uint64_t m;
@@ -560,13 +642,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
                     const int leader = __builtin_ctzll(m);
                     const int v0 = readlane_i(sp.v, leader);
                     const int f0 = readlane_i(f, leader);
-                    int n0 = readlane_i(n, leader);
-                    if (f0 < 0 || (int64_t)f0 + n0 > P.idx.capacity)
-                        n0 = f0 < 0 ? 0 : (int)max((int64_t)0, P.idx.capacity - f0);
+                    const int n0 = clamp_list(f0, readlane_i(n, leader), X.cap);
                     if (v0 != last_v) {
                         for (int e = lane; e < n0; e += 64) {
-                            const int k = ids[f0 + e];
-                            if ((unsigned)k < (unsigned)P.N) atomicOr(&bm[k >> 5], 1u << (k & 31));
+                            const int k = X.ids[f0 + e];
+                            if ((unsigned)k < (unsigned)X.n) atomicOr(&bm[k >> 5], 1u << (k & 31));
                         }
                         last_v = v0;
                     }
@@ -581,14 +661,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
 #pragma unroll
         for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
         for_each_marked(bm, nw, lane, [&](int k) {
-            const cf_ptr r = rec + (size_t)k * REC;
+            const cf_ptr r = X.rec + (size_t)k * REC;
             const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            const cf_ptr lg = lgp + (size_t)k * CP;
+            const cf_ptr lg = X.lgp + (size_t)k * CP;
             float gam = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
@@ -636,14 +716,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
 
         // ---- pass 2: per-primitive adjoint over the union -------------------
         for_each_marked(bm, nw, lane, [&](int k) {
-            const cf_ptr r = rec + (size_t)k * REC;
+            const cf_ptr r = X.rec + (size_t)k * REC;
             const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            const cf_ptr lg = lgp + (size_t)k * CP;
+            const cf_ptr lg = X.lgp + (size_t)k * CP;
             float gam = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
@@ -701,11 +781,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
             constexpr int shift = 6 - Log2<VP>::v;
             const int vi = lane >> shift;
             if (((lane & ((1 << shift) - 1)) == 0) && vi < V && (vi < A_LG || vi - A_LG < P.C))
-                atomicAdd(P.acc + (size_t)k * VP + vi, tot);
+                atomicAdd(acc + (size_t)k * VP + vi, tot);
         });
     }
     if (STATS && rl.valid)
         for (int i = 0; i < 6; ++i) atomicAdd((unsigned long long*)&P.stats[i], (unsigned long long)st[i]);
+}
+
+template <int CP, int KC, bool STATS, bool PERSIST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP, KC), 8))) void k_render_bwd_km(
+    Ctx P) {
+    extern __shared__ uint32_t bm_all[];
+    uint32_t* bm = bm_all + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * P.bitmap_words;
+    for_each_tile<PERSIST>(P, [&](int t) {
+        const int s = find_scene(P.desc, t);
+        bwd_km_tile<CP, KC, STATS>(P, s, t - P.desc->s[s].tile_off, bm);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -714,14 +805,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
 //   g_q = (I - q^ q^T)/|q| * sum_ij G_R_ij dR_ij/dq^
 // ---------------------------------------------------------------------------
 template <int CP>
-__global__ __launch_bounds__(256) void k_finalize(PrimsDev pr, const float* __restrict__ acc, float* g_means,
-                                                  float* g_quats, float* g_scales, float* g_eps, float* g_opacity,
-                                                  float* g_logits) {
+__global__ __launch_bounds__(256) void k_finalize(int n_total, int C, const float* __restrict__ quats,
+                                                  const float* __restrict__ scales, const float* __restrict__ acc,
+                                                  float* g_means, float* g_quats, float* g_scales, float* g_eps,
+                                                  float* g_opacity, float* g_logits) {
     constexpr int VP = AccRow<CP>::P;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= pr.n) return;
+    if (k >= n_total) return;
     const float* a = acc + (size_t)k * VP;
-    const float q0 = pr.quats[4 * k], q1 = pr.quats[4 * k + 1], q2 = pr.quats[4 * k + 2], q3 = pr.quats[4 * k + 3];
+    const float q0 = quats[4 * k], q1 = quats[4 * k + 1], q2 = quats[4 * k + 2], q3 = quats[4 * k + 3];
     const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
     const float w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
     const float R[9] = {1.f - 2.f * (y * y + z * z), 2.f * (x * y - w * z), 2.f * (x * z + w * y),
@@ -732,7 +824,7 @@ __global__ __launch_bounds__(256) void k_finalize(PrimsDev pr, const float* __re
     for (int i = 0; i < 3; ++i) g_means[3 * k + i] = -(R[i] * gx[0] + R[3 + i] * gx[1] + R[6 + i] * gx[2]);
     for (int i = 0; i < 3; ++i) {
         const float d = G[3 * i] * R[3 * i] + G[3 * i + 1] * R[3 * i + 1] + G[3 * i + 2] * R[3 * i + 2];
-        g_scales[3 * k + i] = -d / pr.scales[3 * k + i];
+        g_scales[3 * k + i] = -d / scales[3 * k + i];
     }
     // sum_ij G_ij dR_ij/dq^ for the Hamilton matrix above
     const float gw = -2.f * z * G[1] + 2.f * y * G[2] + 2.f * z * G[3] - 2.f * x * G[5] - 2.f * y * G[6] +
@@ -751,137 +843,232 @@ __global__ __launch_bounds__(256) void k_finalize(PrimsDev pr, const float* __re
     g_eps[2 * k] = a[A_E1];
     g_eps[2 * k + 1] = a[A_E2];
     g_opacity[k] = a[A_SIG];
-    for (int c = 0; c < pr.C; ++c) g_logits[(size_t)k * pr.C + c] = a[A_LG + c];
+    for (int c = 0; c < C; ++c) g_logits[(size_t)k * C + c] = a[A_LG + c];
 }
 
 // ---------------------------------------------------------------------------
-// Host launchers
+// Host side
 // ---------------------------------------------------------------------------
-size_t render_workspace_bytes(int n, int C) {
-    const int CP = padded_classes(C);
-    return align_up((size_t)n * REC * sizeof(float)) + align_up((size_t)n * CP * sizeof(float)) +
-           align_up((size_t)n * acc_row(CP) * sizeof(float));
+static int bitmap_words(int n) { return ((n + 31) / 32 + 63) / 64 * 64; }
+
+void finish_desc(BatchDesc& d, int tile_w) {
+    d.tile_w = tile_w;
+    d.tile_h = 64 / tile_w;
+    int tiles = 0, prims = 0, max_n = 0;
+    int64_t rays = 0, ids = 0;
+    for (int i = 0; i < d.n_scenes; ++i) {
+        SceneDev& S = d.s[i];
+        S.tiles_x = (S.W + d.tile_w - 1) / d.tile_w;
+        S.tiles_y = (S.H + d.tile_h - 1) / d.tile_h;
+        S.tile_off = tiles;
+        S.prim_off = prims;
+        S.ray_off = rays;
+        S.ids_base = ids;
+        tiles += S.cams * S.tiles_x * S.tiles_y;
+        prims += S.n;
+        rays += (int64_t)S.cams * S.H * S.W;
+        ids += S.cap;
+        max_n = std::max(max_n, S.n);
+    }
+    d.total_tiles = tiles;
+    d.total_prims = prims;
+    d.total_rays = rays;
+    d.max_n = max_n;
 }
 
-struct WsLayout {
-    float *rec, *lgp, *acc;
+struct WsSizes {
+    size_t desc, queue, boxes, partials, rec, lgp, acc;
 };
-static WsLayout carve(void* ws, int n, int C) {
-    const int CP = padded_classes(C);
+static WsSizes ws_sizes(const GridDev& g, const BatchDesc& d) {
+    const int CP = padded_classes(d.C);
+    WsSizes z;
+    z.desc = align_up(sizeof(BatchDesc));
+    z.queue = align_up(2 * N_XCD * QUEUE_STRIDE * sizeof(int));
+    z.boxes = align_up((size_t)d.total_prims * sizeof(int4));
+    z.partials = align_up((size_t)d.n_scenes * scan_parts(g) * sizeof(int64_t));
+    z.rec = align_up((size_t)d.total_prims * REC * sizeof(float));
+    z.lgp = align_up((size_t)d.total_prims * CP * sizeof(float));
+    z.acc = align_up((size_t)d.total_prims * acc_row(CP) * sizeof(float));
+    return z;
+}
+
+size_t batch_workspace_bytes(const GridDev& g, const BatchDesc& d) {
+    const WsSizes z = ws_sizes(g, d);
+    return z.desc + z.queue + z.boxes + z.partials + z.rec + z.lgp + z.acc;
+}
+
+size_t index_workspace_bytes(const GridDev& g, const BatchDesc& d) {
+    const WsSizes z = ws_sizes(g, d);
+    return z.desc + z.queue + z.boxes + z.partials;
+}
+
+WsLayout carve_ws(void* ws, const GridDev& g, const BatchDesc& d) {
+    const WsSizes z = ws_sizes(g, d);
     char* p = (char*)ws;
     WsLayout l;
-    l.rec = (float*)p; p += align_up((size_t)n * REC * sizeof(float));
-    l.lgp = (float*)p; p += align_up((size_t)n * CP * sizeof(float));
+    l.desc = (BatchDesc*)p; p += z.desc;
+    l.queue = (int*)p; p += z.queue;
+    l.boxes = (int4*)p; p += z.boxes;
+    l.partials = (int64_t*)p; p += z.partials;
+    l.rec = (float*)p; p += z.rec;
+    l.lgp = (float*)p; p += z.lgp;
     l.acc = (float*)p;
     return l;
 }
 
-static TileMap make_tiles(const RaysDev& rays, const TuneDev& tune) {
-    TileMap tm;
-    tm.tile_w = tune.tile_w;
-    tm.tile_h = 64 / tune.tile_w;
-    tm.tiles_x = (rays.W + tm.tile_w - 1) / tm.tile_w;
-    tm.tiles_y = (rays.H + tm.tile_h - 1) / tm.tile_h;
-    tm.n_tiles = rays.n_cams * tm.tiles_x * tm.tiles_y;
-    return tm;
+void put_desc(const BatchDesc& d, BatchDesc* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, st, d, dst);
+}
+
+hipError_t launch_batch_index(const GridDev& g, const BatchDesc& d, const BatchIO& io, void* ws, hipStream_t st) {
+    const WsLayout l = carve_ws(ws, g, d);
+    put_desc(d, l.desc, st);
+    launch_index_kernels(g, d, l.desc, io, l.boxes, l.partials, st);
+    return hipGetLastError();
+}
+
+static int cu_count() {
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0;
+        int n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            n = 0;
+        cached = n > 0 ? n : 256;
+    }
+    return cached;
+}
+
+template <typename Kern>
+static void launch_tiles(Kern k, bool persistent, const Ctx& P, int wpb, size_t shm, hipStream_t st) {
+    const dim3 block(64 * wpb);
+    const int static_blocks = (P.total_tiles + wpb - 1) / wpb;
+    if (static_blocks == 0) return;
+    if (!persistent) {
+        hipLaunchKernelGGL(k, dim3(static_blocks), block, shm, st, P);
+        return;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, (int)block.x, shm) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    const int blocks = std::min(static_blocks, per_cu * cu_count());
+    hipLaunchKernelGGL(k, dim3(blocks), block, shm, st, P);
 }
 
 template <int CP>
-static void prep(const PrimsDev& pr, const GridDev& g, const WsLayout& l, hipStream_t st) {
-    if (pr.n > 0)
-        hipLaunchKernelGGL(k_prep_records<CP>, dim3((pr.n + 255) / 256), dim3(256), 0, st, pr, g, l.rec, l.lgp);
+static void prep_records(const BatchDesc& d, const GridDev& g, const BatchIO& io, const WsLayout& l,
+                         hipStream_t st) {
+    if (d.total_prims > 0)
+        hipLaunchKernelGGL(k_prep_records<CP>, dim3((d.total_prims + 255) / 256), dim3(256), 0, st, d.total_prims,
+                           d.C, io.means, io.quats, io.scales, io.eps, io.opacity, io.logits, g, l.rec, l.lgp);
+}
+
+static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
+                    const WsLayout& l, int64_t* stats) {
+    Ctx P;
+    P.g = g; P.mr = mr; P.C = d.C; P.total_tiles = d.total_tiles; P.desc = l.desc; P.queue = l.queue;
+    P.counts = io.counts; P.offsets = io.offsets; P.ids = io.ids;
+    P.rec = l.rec; P.lgp = l.lgp; P.origins = io.origins; P.dirs = io.dirs;
+    P.depth = io.depth; P.sem = io.sem; P.probs = io.probs; P.t_final = io.t_final; P.ckpt = io.ckpt;
+    P.g_depth = io.g_depth; P.g_sem = io.g_sem; P.acc = l.acc; P.stats = stats;
+    P.bitmap_words = bitmap_words(d.max_n);
+    return P;
 }
 
 template <int CP>
-static void fwd_dispatch(const FwdParams& P, dim3 grid, dim3 block, hipStream_t st) {
+static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P,
+                    const TuneDev& t, hipStream_t st) {
+    prep_records<CP>(d, g, io, l, st);
     const bool ck = P.ckpt != nullptr, stt = P.stats != nullptr;
-    if (ck && stt) hipLaunchKernelGGL((k_render_fwd<CP, true, true>), grid, block, 0, st, P);
-    else if (ck) hipLaunchKernelGGL((k_render_fwd<CP, true, false>), grid, block, 0, st, P);
-    else if (stt) hipLaunchKernelGGL((k_render_fwd<CP, false, true>), grid, block, 0, st, P);
-    else hipLaunchKernelGGL((k_render_fwd<CP, false, false>), grid, block, 0, st, P);
+    const int wpb = t.waves_per_block;
+    if (stt) {
+        if (ck) launch_tiles(k_render_fwd<CP, true, true, false>, false, P, wpb, 0, st);
+        else launch_tiles(k_render_fwd<CP, false, true, false>, false, P, wpb, 0, st);
+        return;
+    }
+    if (t.persistent) {
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, P.queue, N_XCD * QUEUE_STRIDE, 0);
+        if (ck) launch_tiles(k_render_fwd<CP, true, false, true>, true, P, wpb, 0, st);
+        else launch_tiles(k_render_fwd<CP, false, false, true>, true, P, wpb, 0, st);
+    } else {
+        if (ck) launch_tiles(k_render_fwd<CP, true, false, false>, false, P, wpb, 0, st);
+        else launch_tiles(k_render_fwd<CP, false, false, false>, false, P, wpb, 0, st);
+    }
 }
 
-hipError_t launch_render_fwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
-                             const MarchDev& mr, float* depth, float* sem, float* probs, float* t_final,
-                             float* ckpt, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st) {
-    const int CP = padded_classes(pr.C);
-    const WsLayout l = carve(ws, pr.n, pr.C);
-    FwdParams P;
-    P.g = g; P.idx = idx; P.N = pr.n; P.C = pr.C; P.rec = l.rec; P.lgp = l.lgp; P.rays = rays; P.mr = mr;
-    P.tm = make_tiles(rays, tune);
-    P.depth = depth; P.sem = sem; P.probs = probs; P.t_final = t_final; P.ckpt = ckpt; P.stats = stats;
-    const int wpb = tune.waves_per_block;
-    const dim3 grid((P.tm.n_tiles + wpb - 1) / wpb), block(64 * wpb);
-    switch (CP) {
-        case 4: prep<4>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<4>(P, grid, block, st); break;
-        case 8: prep<8>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<8>(P, grid, block, st); break;
-        case 17: prep<17>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<17>(P, grid, block, st); break;
-        default: prep<32>(pr, g, l, st); if (P.tm.n_tiles) fwd_dispatch<32>(P, grid, block, st); break;
+hipError_t launch_batch_fwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
+                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st) {
+    const WsLayout l = carve_ws(ws, g, d);
+    put_desc(d, l.desc, st);
+    const Ctx P = make_ctx(g, d, mr, io, l, stats);
+    switch (padded_classes(d.C)) {
+        case 4: fwd_run<4>(g, d, io, l, P, tune, st); break;
+        case 8: fwd_run<8>(g, d, io, l, P, tune, st); break;
+        case 17: fwd_run<17>(g, d, io, l, P, tune, st); break;
+        default: fwd_run<32>(g, d, io, l, P, tune, st); break;
     }
     return hipGetLastError();
 }
 
-static int bitmap_words(int n) { return ((n + 31) / 32 + 63) / 64 * 64; }
-
 // The primitive-major backward needs the chunk in registers (K <= 8), a
 // per-wave bitmap that fits the LDS budget, and voxel coordinates that fit the
 // packed form.  Otherwise the sample-major backward runs.
-bool bwd_primitive_major_ok(const GridDev& g, int n, int K, int wpb) {
+bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb) {
     if (!(K == 4 || K == 8)) return false;
     if (g.X > KM_MAX_XY || g.Y > KM_MAX_XY || g.Z > KM_MAX_Z) return false;
-    return (size_t)wpb * bitmap_words(n) * sizeof(uint32_t) <= 64 * 1024;
+    return (size_t)wpb * bitmap_words(max_n) * sizeof(uint32_t) <= 64 * 1024;
+}
+
+template <int CP, int KC>
+static void bwd_km_launch(const Ctx& P, const TuneDev& t, hipStream_t st) {
+    const int wpb = t.waves_per_block;
+    const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);
+    if (P.stats) {
+        launch_tiles(k_render_bwd_km<CP, KC, true, false>, false, P, wpb, shm, st);
+    } else if (t.persistent) {
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, P.queue, N_XCD * QUEUE_STRIDE, 0);
+        launch_tiles(k_render_bwd_km<CP, KC, false, true>, true, P, wpb, shm, st);
+    } else {
+        launch_tiles(k_render_bwd_km<CP, KC, false, false>, false, P, wpb, shm, st);
+    }
 }
 
 template <int CP>
-static void bwd_run(const BwdParams& P, const PrimsDev& pr, const WsLayout& l, int wpb, int bwd_mode, float* g_means,
-                    float* g_quats, float* g_scales, float* g_eps, float* g_opacity, float* g_logits,
-                    hipStream_t st) {
-    prep<CP>(pr, P.g, l, st);
-    const int64_t nacc = (int64_t)pr.n * AccRow<CP>::P;
-    if (nacc > 0) hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((nacc + 255) / 256, 4096)), dim3(256), 0, st,
-                                     l.acc, nacc, 0.0f);
-    if (P.tm.n_tiles) {
-        const dim3 grid((P.tm.n_tiles + wpb - 1) / wpb), block(64 * wpb);
-        const bool km = bwd_mode != 1 && bwd_primitive_major_ok(P.g, P.N, P.mr.K, wpb);
-        if (km) {
-            BwdParams Q = P;
-            Q.bitmap_words = bitmap_words(pr.n);
-            const size_t shm = (size_t)wpb * Q.bitmap_words * sizeof(uint32_t);
-            if (P.mr.K == 4) {
-                if (P.stats) hipLaunchKernelGGL((k_render_bwd_km<CP, 4, true>), grid, block, shm, st, Q);
-                else hipLaunchKernelGGL((k_render_bwd_km<CP, 4, false>), grid, block, shm, st, Q);
-            } else {
-                if (P.stats) hipLaunchKernelGGL((k_render_bwd_km<CP, 8, true>), grid, block, shm, st, Q);
-                else hipLaunchKernelGGL((k_render_bwd_km<CP, 8, false>), grid, block, shm, st, Q);
-            }
-        } else {
-            const size_t shm = (size_t)wpb * 4 * P.mr.K * 64 * sizeof(float);
-            if (P.stats) hipLaunchKernelGGL((k_render_bwd<CP, true>), grid, block, shm, st, P);
-            else hipLaunchKernelGGL((k_render_bwd<CP, false>), grid, block, shm, st, P);
-        }
+static void bwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P,
+                    const TuneDev& t, hipStream_t st) {
+    prep_records<CP>(d, g, io, l, st);
+    const int64_t nacc = (int64_t)d.total_prims * AccRow<CP>::P;
+    if (nacc > 0)
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<int64_t>((nacc + 255) / 256, 4096)), dim3(256), 0, st,
+                           l.acc, nacc, 0.0f);
+    const int wpb = t.waves_per_block;
+    const bool km = t.bwd_mode != 1 && bwd_primitive_major_ok(g, d.max_n, P.mr.K, wpb);
+    if (km) {
+        if (P.mr.K == 4) bwd_km_launch<CP, 4>(P, t, st);
+        else bwd_km_launch<CP, 8>(P, t, st);
+    } else {
+        const size_t shm = (size_t)wpb * 3 * P.mr.K * 64 * sizeof(float);
+        if (P.stats) launch_tiles(k_render_bwd<CP, true>, false, P, wpb, shm, st);
+        else launch_tiles(k_render_bwd<CP, false>, false, P, wpb, shm, st);
     }
-    if (pr.n > 0)
-        hipLaunchKernelGGL(k_finalize<CP>, dim3((pr.n + 255) / 256), dim3(256), 0, st, pr, (const float*)l.acc,
-                           g_means, g_quats, g_scales, g_eps, g_opacity, g_logits);
+    if (d.total_prims > 0)
+        hipLaunchKernelGGL(k_finalize<CP>, dim3((d.total_prims + 255) / 256), dim3(256), 0, st, d.total_prims, d.C,
+                           io.quats, io.scales, (const float*)l.acc, io.g_means, io.g_quats, io.g_scales, io.g_eps,
+                           io.g_opacity, io.g_logits);
 }
 
-hipError_t launch_render_bwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
-                             const MarchDev& mr, const float* ckpt, const float* g_depth, const float* g_sem,
-                             float* g_means, float* g_quats, float* g_scales, float* g_eps, float* g_opacity,
-                             float* g_logits, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st) {
-    const int CP = padded_classes(pr.C);
-    const WsLayout l = carve(ws, pr.n, pr.C);
-    BwdParams P;
-    P.stats = stats;
-    P.g = g; P.idx = idx; P.N = pr.n; P.C = pr.C; P.rec = l.rec; P.lgp = l.lgp; P.rays = rays; P.mr = mr;
-    P.tm = make_tiles(rays, tune);
-    P.ckpt = ckpt; P.g_depth = g_depth; P.g_sem = g_sem; P.acc = l.acc;
-    const int wpb = tune.waves_per_block;
-    switch (CP) {
-        case 4: bwd_run<4>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
-        case 8: bwd_run<8>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
-        case 17: bwd_run<17>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
-        default: bwd_run<32>(P, pr, l, wpb, tune.bwd_mode, g_means, g_quats, g_scales, g_eps, g_opacity, g_logits, st); break;
+hipError_t launch_batch_bwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
+                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st) {
+    const WsLayout l = carve_ws(ws, g, d);
+    put_desc(d, l.desc, st);
+    Ctx P = make_ctx(g, d, mr, io, l, stats);
+    P.queue = l.queue + N_XCD * QUEUE_STRIDE;   // the backward's own counters
+    switch (padded_classes(d.C)) {
+        case 4: bwd_run<4>(g, d, io, l, P, tune, st); break;
+        case 8: bwd_run<8>(g, d, io, l, P, tune, st); break;
+        case 17: bwd_run<17>(g, d, io, l, P, tune, st); break;
+        default: bwd_run<32>(g, d, io, l, P, tune, st); break;
     }
     return hipGetLastError();
 }

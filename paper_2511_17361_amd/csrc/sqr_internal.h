@@ -1,4 +1,11 @@
-// Host-side interface between the C ABI layer and the kernel launchers.
+// Interface between the C ABI layer and the kernel launchers.
+//
+// Every launcher works on a batch of scenes that share one voxel grid, one ray
+// march and one class count; a single-scene call is a batch of one.  All
+// per-scene arrays are concatenated scene-major.  The per-scene layout lives in
+// a small table (BatchDesc) that the launchers write into the workspace with a
+// kernel before the render kernels read it, so a launch sequence contains no
+// host->device copies and can be captured into a hipGraph.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,47 +19,72 @@ namespace sqr {
 constexpr size_t WS_ALIGN = 256;
 inline size_t align_up(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
 
-// ---------------- index ----------------
-size_t index_workspace_bytes(int64_t nvox, int n);
-hipError_t launch_build_index(const GridDev& g, const float* means, int n, int32_t* counts, int32_t* offsets,
-                              int32_t* ids, int64_t capacity, int64_t* total, void* ws, hipStream_t st);
+constexpr int MAX_SCENES = 32;
+constexpr int QUEUE_STRIDE = 32;      // ints between the per-XCD work counters (128 B)
+constexpr int N_XCD = 8;
 
-// ---------------- render ----------------
-struct PrimsDev {
-    int n, C;
-    const float *means, *quats, *scales, *eps, *opacity, *logits;
+// One scene of a batch (device-side view).
+struct SceneDev {
+    int n;            // primitives of the scene
+    int prim_off;     // its first primitive in the concatenated arrays
+    int cams, H, W;   // its rays
+    int tiles_x, tiles_y;
+    int tile_off;     // its first tile in the global tile order
+    int64_t ids_base; // its first slot in the concatenated id lists
+    int64_t cap;      // id slots reserved for it
+    int64_t ray_off;  // its first ray in the concatenated ray arrays
 };
-struct RaysDev {
-    int n_cams, H, W;
-    const float *origins, *dirs;
+
+struct BatchDesc {
+    int n_scenes;
+    int C;            // classes
+    int total_prims, total_tiles, max_n;
+    int tile_w, tile_h;
+    int64_t total_rays;
+    SceneDev s[MAX_SCENES];
 };
+
 struct MarchDev {
     int L;
     float t_near, delta;
     int K;      // checkpoint spacing (0 = none)
 };
-struct IndexDev {
-    const int32_t *counts, *offsets, *ids;
-    int64_t capacity;
-};
+
 struct TuneDev {
     int tile_w;           // 4, 8 or 16 (tile is tile_w x 64/tile_w pixels)
     int waves_per_block;  // 1..4
     int bwd_mode;         // 0 auto, 1 sample-major, 2 primitive-major
+    int persistent;       // 0 static tile grid, 1 persistent waves with per-XCD work queues
+};
+
+// Device pointers of one batch call (concatenated scene-major).
+struct BatchIO {
+    const float *means, *quats, *scales, *eps, *opacity, *logits;
+    const float *origins, *dirs;
+    int32_t *counts, *offsets, *ids;
+    int64_t* totals;
+    float *depth, *sem, *probs, *t_final, *ckpt;
+    const float *g_depth, *g_sem;
+    float *g_means, *g_quats, *g_scales, *g_eps, *g_opacity, *g_logits;
 };
 
 // class count padded to the compiled widths
 int padded_classes(int C);
 
-size_t render_workspace_bytes(int n, int C);
-hipError_t launch_render_fwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
-                             const MarchDev& mr, float* depth, float* sem, float* probs, float* t_final,
-                             float* ckpt, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
+// Fills the tile counts and offsets of a host-side batch description.
+void finish_desc(BatchDesc& d, int tile_w);
+
+size_t batch_workspace_bytes(const GridDev& g, const BatchDesc& d);
+// the front part of the same layout that the index build alone uses
+size_t index_workspace_bytes(const GridDev& g, const BatchDesc& d);
+
+hipError_t launch_batch_index(const GridDev& g, const BatchDesc& d, const BatchIO& io, void* ws, hipStream_t st);
+hipError_t launch_batch_fwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
+                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
+hipError_t launch_batch_bwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
+                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
+
 // whether the primitive-major backward applies to these arguments
-bool bwd_primitive_major_ok(const GridDev& g, int n, int K, int wpb);
-hipError_t launch_render_bwd(const GridDev& g, const IndexDev& idx, const PrimsDev& pr, const RaysDev& rays,
-                             const MarchDev& mr, const float* ckpt, const float* g_depth, const float* g_sem,
-                             float* g_means, float* g_quats, float* g_scales, float* g_eps, float* g_opacity,
-                             float* g_logits, int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
+bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb);
 
 }  // namespace sqr

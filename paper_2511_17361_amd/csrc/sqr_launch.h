@@ -1,0 +1,33 @@
+// Workspace layout and cross-file launch helpers (host side).
+#pragma once
+
+#include "sqr_internal.h"
+
+namespace sqr {
+
+// Caller workspace, carved in this order (each part 256-byte aligned):
+//   desc      device copy of the batch description (written by a kernel)
+//   queue     2 x 8 per-XCD work counters (forward, backward), 128 B apart
+//   boxes     [total_prims] packed neighbourhood boxes (index build)
+//   partials  [n_scenes x scan parts] scan partial sums (index build)
+//   rec       [total_prims x REC] prepared primitive records
+//   lgp       [total_prims x CP] logits padded to the compiled class width
+//   acc       [total_prims x VP] backward gradient accumulators
+struct WsLayout {
+    BatchDesc* desc;
+    int* queue;
+    int4* boxes;
+    int64_t* partials;
+    float* rec;
+    float* lgp;
+    float* acc;
+};
+
+int acc_row(int CP);
+int scan_parts(const GridDev& g);
+WsLayout carve_ws(void* ws, const GridDev& g, const BatchDesc& d);
+void put_desc(const BatchDesc& d, BatchDesc* dst, hipStream_t st);
+void launch_index_kernels(const GridDev& g, const BatchDesc& d, const BatchDesc* desc_dev, const BatchIO& io,
+                          int4* boxes, int64_t* partials, hipStream_t st);
+
+}  // namespace sqr

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_defaults():
     lib = L.load()
-    assert lib.sq_version() >= 100
+    assert lib.sq_version() >= 200
     t = lib.sq_default_tuning()
     assert t.tile_w in (4, 8, 16) and 1 <= t.waves_per_block <= 4
 
@@ -113,7 +113,7 @@ def test_render_fwd_rejects_bad_arguments_without_launch(mutate, code):
     args = dict(grid=_grid(), prims=_prims(), rays=_rays(), march=_march(), index=_index(), ws_bytes=1 << 30,
                 tile_w=8)
     mutate(args)
-    t = L.SqTuning(args["tile_w"], 4, 0)
+    t = L.SqTuning(args["tile_w"], 4, 0, 0, 0)
     rc = lib.sq_render_fwd(ct.byref(args["grid"]), ct.byref(args["index"]), ct.byref(args["prims"]),
                            ct.byref(args["rays"]), ct.byref(args["march"]), FAKE, FAKE, None, FAKE, None, None,
                            ct.byref(t), 0x100000, args["ws_bytes"], None)

@@ -1,0 +1,187 @@
+"""GPU tests of the batched form: several scenes with uneven primitive and
+camera counts in single launches (static and persistent tile scheduling), the
+hipGraph-captured step and the autotuner.  Each scene of a batch must match
+its own single-scene render (forward bit for bit: the same tile code runs) and
+the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.scenes_small import random_scene
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2511_17361_amd import api
+    from tests import gpu_helpers as H
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _small_batch(seed=60, ns=(5, 0, 23, 11), sizes=((19, 13), (7, 5), (33, 9), (16, 16)), C=5):
+    scenes = []
+    for i, (n, (w, h)) in enumerate(zip(ns, sizes)):
+        sc = random_scene(seed + i, n=n, n_classes=C, width=w, height=h, n_samples=29, opacity_hi=0.8,
+                          dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0)
+        scenes.append(sc)
+    return scenes
+
+
+def _make_batch(scenes, K=4, probs=True):
+    grid = api.Grid.of(scenes[0].grid)
+    march = api.March(scenes[0].march.n_samples, scenes[0].march.t_near, scenes[0].march.t_far, K)
+    dev = [(api.Prims.from_numpy(s.prims), api.Rays.from_numpy(s.rays)) for s in scenes]
+    return api.Batch(grid, march, dev, probs=probs)
+
+
+def _upstream(scenes, seed):
+    rng = np.random.default_rng(seed)
+    return [synth.upstream_grads(rng, s.rays, s.prims.n_classes) for s in scenes]
+
+
+@pytest.mark.parametrize("tune", [api.Tuning(8, 4, 0, 0, 0), api.Tuning(4, 2, 0, 1, 0), api.Tuning(16, 1, 2, 1, 8),
+                                  api.Tuning(8, 4, 1, 0, 16)] if torch.cuda.is_available() else [None])
+def test_batch_matches_single_scenes_and_oracle(tune):
+    scenes = _small_batch()
+    _say("batch small", tune)
+    b = _make_batch(scenes)
+    ups = _upstream(scenes, 1)
+    for i, (gd, gs) in enumerate(ups):
+        b.set_upstream(i, torch.from_numpy(gd).cuda(), torch.from_numpy(gs).cuda())
+    b.build_index()
+    b.render_fwd(tune)
+    b.render_bwd(tune)
+    torch.cuda.synchronize()
+    totals = b.buf["totals"].cpu().numpy()
+    K = tune.chunk or 4
+    for i, sc in enumerate(scenes):
+        out = {k: v.cpu().numpy() for k, v in b.scene_outputs(i).items()}
+        # index of this scene
+        c, o, ids, t = oracle.build_index(sc.prims.means, sc.grid)
+        assert totals[i] == t
+        n0, n, r0, cams, Hh, Ww = b.scene_slices(i)
+        V = sc.grid.n_voxels
+        np.testing.assert_array_equal(b.buf["counts"][i * V:(i + 1) * V].cpu().numpy(), c)
+        np.testing.assert_array_equal(b.buf["offsets"][i * V:(i + 1) * V].cpu().numpy(), o)
+        base = sum(b.caps[:i])
+        np.testing.assert_array_equal(b.buf["ids"][base:base + t].cpu().numpy(), ids)
+        # single-scene render with the same tuning: forward bit for bit
+        single, _ = H.run_fwd(sc, tuning=api.Tuning(tune.tile_w, tune.waves_per_block))
+        for k in ("depth", "sem", "t_final", "probs"):
+            assert np.array_equal(out[k], single[k]), (i, k)
+        ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march)
+        H.assert_depth_close(out["depth"], ref["depth"], f"scene {i}")
+        H.assert_probs_close(out["probs"], ref["probs"], f"scene {i}")
+        gd, gs = ups[i]
+        gref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, gd, gs)
+        got = {k: out["g_" + k] for k in ("means", "quats", "scales", "eps", "opacity", "logits")}
+        if sc.prims.n:
+            H.assert_grads_close(got, gref, f"scene {i} K{K}")
+
+
+def test_persistent_forward_is_bitwise_static_forward():
+    scenes = _small_batch(seed=70)
+    b = _make_batch(scenes)
+    b.build_index()
+    b.render_fwd(api.Tuning(8, 4, 0, 0, 0))
+    torch.cuda.synchronize()
+    a = {k: b.buf[k].clone() for k in ("depth", "sem", "t_final")}
+    b.render_fwd(api.Tuning(8, 4, 0, 1, 0))
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b.buf[k]), k
+
+
+def test_graph_replays_match_eager_step():
+    scenes = _small_batch(seed=80)
+    b = _make_batch(scenes)
+    for i, (gd, gs) in enumerate(_upstream(scenes, 2)):
+        b.set_upstream(i, torch.from_numpy(gd).cuda(), torch.from_numpy(gs).cuda())
+    tune = api.Tuning(8, 4, 0, 1, 4)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.step(tune, stream=s)
+    torch.cuda.synchronize()
+    eager = {k: b.buf[k].clone() for k in ("depth", "sem", "t_final", "ckpt", "g_means", "g_logits", "g_opacity")}
+    b.capture(tune, stream=s)
+    for rep in range(3):
+        # clobber outputs and run unrelated eager work between replays
+        for k in eager:
+            b.buf[k].fill_(-7.0)
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        b.replay(stream=s)
+        torch.cuda.synchronize()
+        for k in ("depth", "sem", "t_final", "ckpt"):
+            assert torch.equal(eager[k], b.buf[k]), (rep, k)
+        for k in ("g_means", "g_logits", "g_opacity"):
+            torch.testing.assert_close(b.buf[k], eager[k], rtol=1e-4, atol=1e-5)
+        del junk
+    b.release_graph()
+
+
+def test_autotune_returns_a_timed_candidate():
+    scenes = _small_batch(seed=90)
+    b = _make_batch(scenes)
+    cands = [api.Tuning(8, 4, 0, 0, 4), api.Tuning(16, 2, 0, 1, 8), api.Tuning(4, 4, 1, 0, 16)]
+    best, ms = b.autotune(cands, reps=2)
+    assert best in cands and len(ms) == 3 and all(m > 0 for m in ms)
+    assert ms[cands.index(best)] == min(ms)
+
+
+def test_batch_rejects_bad_tuning_without_launch():
+    scenes = _small_batch(seed=95)
+    b = _make_batch(scenes)
+    with pytest.raises(Exception, match="status -1"):
+        b.render_fwd(api.Tuning(tile_w=5))
+    with pytest.raises(Exception, match="status -1"):
+        b.render_bwd(api.Tuning(chunk=3))
+
+
+def test_config3_batch_equals_single_scene_renders():
+    """Config 3 workload: 8 scenes, {2k..25.6k} superquadrics, 6 cameras at
+    352x200 each, L=100: each scene of the persistent batched forward equals
+    its single-scene render bit for bit; two scenes are spot-checked against
+    the oracle on sampled rays, and the batched backward of the smallest scene
+    against the oracle with sparse upstream gradients."""
+    scenes = [synth.config(3, s) for s in range(8)]
+    _say("config3 batch")
+    b = _make_batch(scenes)
+    rng = np.random.default_rng(3)
+    ids0 = rng.choice(scenes[0].rays.n_rays, 800, replace=False)
+    for i, sc in enumerate(scenes):
+        gd = np.zeros(sc.rays.n_rays, np.float32)
+        gs = np.zeros((sc.rays.n_rays, sc.prims.n_classes), np.float32)
+        if i == 0:
+            gd[ids0] = rng.standard_normal(ids0.size)
+            gs[ids0] = rng.standard_normal((ids0.size, sc.prims.n_classes))
+        cams, Hh, Ww = sc.rays.shape
+        b.set_upstream(i, torch.from_numpy(gd.reshape(cams, Hh, Ww)).cuda(),
+                       torch.from_numpy(gs.reshape(cams, Hh, Ww, -1).transpose(0, 3, 1, 2).copy()).cuda())
+    tune = api.Tuning(8, 4, 0, 1, 4)
+    b.step(tune)
+    torch.cuda.synchronize()
+    for i, sc in enumerate(scenes):
+        out = {k: v.cpu().numpy() for k, v in b.scene_outputs(i).items()}
+        single, _ = H.run_fwd(sc)
+        for k in ("depth", "sem", "t_final"):
+            assert np.array_equal(out[k], single[k]), (i, k)
+        if i in (0, 7):
+            rid = np.random.default_rng(i).choice(sc.rays.n_rays, 400, replace=False)
+            ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march, ray_ids=rid)
+            H.assert_depth_close(out["depth"].reshape(-1)[rid], ref["depth"], f"cfg3 scene {i}")
+            H.assert_probs_close(H.flat_sem(out["probs"])[rid], ref["probs"], f"cfg3 scene {i}")
+    sc = scenes[0]
+    gd = b.buf["g_depth"][:sc.rays.n_rays].cpu().numpy()
+    C = sc.prims.n_classes
+    gs_img = b.scene_outputs(0)  # noqa: F841 (outputs already checked)
+    gsem = b.buf["g_sem"][:sc.rays.n_rays * C].cpu().numpy().reshape(6, C, 200, 352).transpose(0, 2, 3, 1)
+    gref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, gd[ids0], gsem.reshape(-1, C)[ids0],
+                              ray_ids=ids0)
+    got = {k: b.scene_outputs(0)["g_" + k].cpu().numpy() for k in ("means", "quats", "scales", "eps", "opacity",
+                                                                     "logits")}
+    H.assert_grads_close(got, gref, "cfg3 scene 0")
