@@ -133,9 +133,9 @@ typedef struct {
  *                   per block) and the sample-major one otherwise; the other
  *                   values force one of them (forcing primitive-major where it
  *                   does not apply returns SQ_ERR_UNSUPPORTED).
- *  persistent       0: one wavefront per ray tile; 1: persistent wavefronts
- *                   that take tiles from eight per-XCD work queues (each XCD
- *                   drains a contiguous range of tiles, then steals).
+ *  persistent       0: one wavefront per ray tile; 1 (default): persistent
+ *                   wavefronts that take tiles from eight per-XCD work queues
+ *                   (each XCD drains a contiguous range of tiles, then steals).
  *  chunk            batched calls: checkpoint spacing K (4, 8 or 16) used by
  *                   the forward's checkpoints and the backward; 0 = the
  *                   batch's march.ckpt_every.  Single-scene calls always use

@@ -136,7 +136,7 @@ class Tuning:
     tile_w: int = 8
     waves_per_block: int = 4
     bwd_mode: int = L.SQ_BWD_AUTO
-    persistent: int = 0
+    persistent: int = 1
     chunk: int = 0
 
     def c(self) -> L.SqTuning:

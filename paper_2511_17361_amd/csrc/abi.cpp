@@ -86,7 +86,7 @@ sq_tuning default_tuning() {
     t.tile_w = 8;
     t.waves_per_block = 4;
     t.bwd_mode = SQ_BWD_AUTO;
-    t.persistent = 0;
+    t.persistent = 1;
     t.chunk = 0;
     return t;
 }

@@ -2,11 +2,15 @@
 //
 // Mapping: one wavefront = one tile of 64 rays (tile_w x 64/tile_w pixels of
 // one camera of one scene).  Rays of a tile are nearly parallel, so at a given
-// sample index most lanes sit in the same voxel.  Per sample the wave walks the
-// distinct voxels of its active lanes one at a time; inside one voxel the
-// primitive id, its prepared record and its logits are wave-uniform and arrive
-// through the scalar data cache, and each lane evaluates p_o at its own sample
-// point.  Nothing here is a dense contraction, so there is no MFMA use.
+// sample index most lanes sit in the same voxel.  When they all do, the wave
+// walks that voxel's list; otherwise it walks the union of the lists of its
+// lanes' voxels (built in a per-wave LDS bitmap, ascending id) and each lane
+// takes the primitives whose neighbourhood box holds its voxel -- exactly its
+// own list, in the same ascending order, so the result does not depend on how
+// the lanes group.  The primitive id, its prepared record and its logits are
+// wave-uniform and arrive through the scalar data cache; each lane evaluates
+// p_o at its own sample point.  Nothing here is a dense contraction, so there
+// is no MFMA use.
 //
 // Tiles of all scenes of a batch form one global tile order.  Waves take tiles
 // either from a static grid (one wave per tile, XCD-grouped block order) or,
@@ -42,7 +46,8 @@ int padded_classes(int C) {
 int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
 
 // Occupancy targets (waves per SIMD) that the register allocator must meet.
-#define FWD_WPE(CP) ((CP) <= 8 ? 6 : (CP) <= 17 ? 4 : 3)
+#define FWD_WPE(CP, CKPT, STATS, PERSIST) \
+    ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : !(CKPT) ? 6 : (PERSIST) ? 5 : 4)
 #define BWD_WPE(CP, KC) ((KC) == 4 && (CP) <= 17 ? 4 : 3)
 
 // Kernel parameters shared by every render kernel.
@@ -60,7 +65,7 @@ struct Ctx {
     const float *g_depth, *g_sem;
     float* acc;
     int64_t* stats;
-    int bitmap_words;           // per-wave bitmap size of the primitive-major backward
+    int bitmap_words;           // per-wave union bitmap size (0: none)
 };
 
 // ---------------------------------------------------------------------------
@@ -121,6 +126,26 @@ __global__ __launch_bounds__(64) void k_put_desc(BatchDesc d, BatchDesc* __restr
 // ---------------------------------------------------------------------------
 // Tile scheduling and lane setup
 // ---------------------------------------------------------------------------
+// The kernel's argument block (every render kernel takes one Ctx, at offset 0
+// of the kernel argument segment) read through a pointer the compiler cannot
+// see through.  Persistent loops read it once per tile: otherwise every field
+// load is hoisted out of the loop and stays live in scalar registers, which
+// then spill.
+// (The host pass of hipcc cannot bind a constant-address-space object to the
+// implicit copy constructor, so it sees a stub; only device code runs this.)
+template <typename T>
+__device__ __forceinline__ T kernel_arg0() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) T* KPtr;
+    KPtr p = (KPtr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    const T c = *p;
+    return c;
+#else
+    return T();
+#endif
+}
+
 template <bool PERSIST, typename F>
 __device__ __forceinline__ void for_each_tile(const Ctx& P, F&& body) {
     const int wpb = blockDim.x >> 6;
@@ -129,7 +154,7 @@ __device__ __forceinline__ void for_each_tile(const Ctx& P, F&& body) {
         // wave-uniform by construction; readfirstlane tells the compiler so, which
         // keeps everything derived from the tile (scene, pointers) in SGPRs
         const int t = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * wpb + (threadIdx.x >> 6));
-        if (t < total) body(t);
+        if (t < total) body(t, P);
         return;
     }
     const int lane = threadIdx.x & 63;
@@ -144,7 +169,7 @@ __device__ __forceinline__ void for_each_tile(const Ctx& P, F&& body) {
             if (lane == 0) t = atomicAdd(&P.queue[x * QUEUE_STRIDE], 1);
             t = __builtin_amdgcn_readlane(t, 0);
             if (lo + t >= hi) break;
-            body(lo + t);
+            body(lo + t, kernel_arg0<Ctx>());
         }
     }
 }
@@ -228,17 +253,64 @@ __device__ __forceinline__ int clamp_list(int f0, int n0, int64_t cap) {
 }
 
 // ---------------------------------------------------------------------------
+// Per-wave union of voxel lists
+//
+// The index lists primitive k in voxel v exactly when v lies in k's clipped
+// neighbourhood box (the packed box of its record), so a lane can test
+// membership of any primitive in its own voxel's list from the record alone.
+// A per-wave LDS bitmap with one bit per primitive of the scene enumerates the
+// union of several lists in ascending id.
+// ---------------------------------------------------------------------------
+constexpr int PV_BITS_X = 11, PV_BITS_Y = 11;    // packed voxel: ix | iy << 11 | iz << 22
+constexpr int KM_MAX_XY = (1 << 11) - 1, KM_MAX_Z = (1 << 9) - 1;
+
+__device__ __forceinline__ int pack_voxel(int ix, int iy, int iz) {
+    return ix | (iy << PV_BITS_X) | (iz << (PV_BITS_X + PV_BITS_Y));
+}
+
+// k listed in packed voxel pv (pv < 0: dead sample)?
+__device__ __forceinline__ bool listed_in(int pv, int bx, int by, int bz) {
+    const int ix = pv & ((1 << PV_BITS_X) - 1);
+    const int iy = (pv >> PV_BITS_X) & ((1 << PV_BITS_Y) - 1);
+    const int iz = (int)((unsigned)pv >> (PV_BITS_X + PV_BITS_Y));
+    return (pv >= 0) & in_range(ix, bx) & in_range(iy, by) & in_range(iz, bz);
+}
+
+// Visit the set bits of a per-wave bitmap in ascending order (wave-uniform);
+// with CLEAR the words are zeroed as they are read.
+template <bool CLEAR = false, typename F>
+__device__ __forceinline__ void for_each_marked(uint32_t* bm, int nw, int lane, F&& body) {
+    for (int wb = 0; wb < nw; wb += 64) {
+        const uint32_t word = bm[wb + lane];
+        if (CLEAR && word != 0u) bm[wb + lane] = 0u;
+        uint64_t nz = wave_ballot(word != 0u);
+        while (nz) {
+            const int l = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)word, l);
+            while (wv) {
+                const int b = __builtin_ctz(wv);
+                wv &= wv - 1;
+                body(((wb + l) << 5) + b);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
 template <int CP, bool CKPT, bool STATS>
-__device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile) {
+__device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t* bm) {
     const SceneDev& S = P.desc->s[s];
     const RayLane rl = setup_lane(P, S, tile);
     const SceneIndex X = scene_index<CP>(P, s, S);
+    const int lane = threadIdx.x & 63;
+    const int nw = ((X.n + 31) / 32 + 63) / 64 * 64;     // bitmap words of this scene
     const int L = P.mr.L, K = P.mr.K;
     const int64_t R = (int64_t)S.cams * S.H * S.W;
     const int nck = CKPT ? (L + K - 1) / K : 0;
-    float* ckpt = CKPT ? P.ckpt + (int64_t)nck * S.ray_off : nullptr;
+    float* ckpt = CKPT ? P.ckpt + (int64_t)nck * S.ray_off + lane_lray(rl, S) : nullptr;
 
     float T = rl.valid ? 1.0f : 0.0f;
     float D = 0.0f;
@@ -260,39 +332,83 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile) {
             n_nxt = 0; f_nxt = 0;
             if (alive && nxt.v >= 0) { n_nxt = X.counts[nxt.v]; f_nxt = X.offsets[nxt.v]; }
         }
-        if (CKPT && (j % K) == 0 && rl.valid) ckpt[(int64_t)(j / K) * R + lane_lray(rl, S)] = T;
+        if (CKPT && (j % K) == 0 && rl.valid) ckpt[(int64_t)(j / K) * R] = T;
 
         const bool act = alive && (cur.v >= 0) && (n > 0);
-        if (wave_ballot(act) != 0) {
+        const uint64_t am = wave_ballot(act);
+        if (am != 0) {
+            // Eq. eq:alpha_sem_sq: a = sum_k p_k sigma_k and s = sum_k p_k c_k over
+            // the lane's own list, ascending id
             float a = 0.0f;
             float sv[CP];
 #pragma unroll
             for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
             if (STATS && act) { ++st_samples; st_pairs += n; }
-            bool pend = act;
-            uint64_t m;
-            while ((m = wave_ballot(pend)) != 0) {
-                const int leader = __builtin_ctzll(m);
-                const int v0 = readlane_i(cur.v, leader);
-                const int f0 = readlane_i(f, leader);
-                const int n0 = clamp_list(f0, readlane_i(n, leader), X.cap);
-                const bool mine = pend && (cur.v == v0);
-                if (mine) {
+            auto add_pair = [&](int k) {
+                const cf_ptr r = X.rec + (size_t)k * REC;
+                const float p = eval_p(r, cur.x, cur.y, cur.z);
+                if (STATS && pair_kept(r, cur.x, cur.y, cur.z)) ++st_nz;
+                if (p != 0.0f) {
+                    a = fmaf(p, r[15], a);
+                    const cf_ptr lg = X.lgp + (size_t)k * CP;
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
+                }
+            };
+            const int lead = __builtin_ctzll(am);
+            const int v_lead = readlane_i(cur.v, lead);
+            if (wave_ballot(act && cur.v != v_lead) == 0) {
+                // one voxel for every active lane: walk its list
+                const int f0 = readlane_i(f, lead);
+                const int n0 = clamp_list(f0, readlane_i(n, lead), X.cap);
+                if (act) {
                     for (int e = 0; e < n0; ++e) {
                         const int k = X.ids[f0 + e];
-                        if ((unsigned)k >= (unsigned)X.n) continue;
-                        const cf_ptr r = X.rec + (size_t)k * REC;
-                        const float p = eval_p(r, cur.x, cur.y, cur.z);
-                        if (STATS && pair_kept(r, cur.x, cur.y, cur.z)) ++st_nz;
-                        if (p != 0.0f) {
-                            a = fmaf(p, r[15], a);
-                            const cf_ptr lg = X.lgp + (size_t)k * CP;
-#pragma unroll
-                            for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
-                        }
+                        if ((unsigned)k < (unsigned)X.n) add_pair(k);
                     }
                 }
-                pend = pend && !mine;
+            } else if (bm) {
+                // several voxels: mark the union of their lists, then walk it
+                bool pend = act;
+                uint64_t m;
+                while ((m = wave_ballot(pend)) != 0) {
+                    const int g = __builtin_ctzll(m);
+                    const int vg = readlane_i(cur.v, g);
+                    const int fg = readlane_i(f, g);
+                    const int ng = clamp_list(fg, readlane_i(n, g), X.cap);
+                    for (int e = lane; e < ng; e += 64) {
+                        const int k = X.ids[fg + e];
+                        if ((unsigned)k < (unsigned)X.n) atomicOr(&bm[k >> 5], 1u << (k & 31));
+                    }
+                    pend = pend && (cur.v != vg);
+                }
+                wave_lds_sync();
+                for_each_marked<true>(bm, nw, lane, [&](int k) {
+                    const cf_ptr r = X.rec + (size_t)k * REC;
+                    const bool mem = act && in_range(cur.ix, __float_as_int(r[20])) &&
+                                     in_range(cur.iy, __float_as_int(r[21])) &&
+                                     in_range(cur.iz, __float_as_int(r[22]));
+                    if (mem) add_pair(k);
+                });
+                wave_lds_sync();
+            } else {
+                // several voxels, no bitmap: one voxel group at a time
+                bool pend = act;
+                uint64_t m;
+                while ((m = wave_ballot(pend)) != 0) {
+                    const int g = __builtin_ctzll(m);
+                    const int vg = readlane_i(cur.v, g);
+                    const int fg = readlane_i(f, g);
+                    const int ng = clamp_list(fg, readlane_i(n, g), X.cap);
+                    const bool mine = pend && (cur.v == vg);
+                    if (mine) {
+                        for (int e = 0; e < ng; ++e) {
+                            const int k = X.ids[fg + e];
+                            if ((unsigned)k < (unsigned)X.n) add_pair(k);
+                        }
+                    }
+                    pend = pend && !mine;
+                }
             }
             // Eq. eq:alpha_composite and eq:depth_sem
             const float alpha = fminf(a, 1.0f);
@@ -306,7 +422,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile) {
         if (wave_ballot(alive) == 0) {
             // every later sample of this tile is exactly zero
             if (CKPT && rl.valid)
-                for (int c = j / K + 1; c * K < L; ++c) ckpt[(int64_t)c * R + lane_lray(rl, S)] = T;
+                for (int c = j / K + 1; c * K < L; ++c) ckpt[(int64_t)c * R] = T;
             break;
         }
     }
@@ -348,11 +464,21 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile) {
     }
 }
 
+// Dynamic LDS: waves_per_block x bitmap_words words (zero bitmap_words: no
+// union bitmap; mixed-voxel samples then walk one voxel group at a time).
 template <int CP, bool CKPT, bool STATS, bool PERSIST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP), 8))) void k_render_fwd(Ctx P) {
-    for_each_tile<PERSIST>(P, [&](int t) {
-        const int s = find_scene(P.desc, t);
-        fwd_tile<CP, CKPT, STATS>(P, s, t - P.desc->s[s].tile_off);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP, CKPT, STATS, PERSIST), 8))) void k_render_fwd(Ctx P) {
+    extern __shared__ uint32_t bm_all[];
+    uint32_t* bm = nullptr;
+    if (P.bitmap_words > 0) {
+        bm = bm_all + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * P.bitmap_words;
+        // the walks clear the words they read, so one clear per wave suffices
+        for (int w = (int)(threadIdx.x & 63); w < P.bitmap_words; w += 64) bm[w] = 0u;
+        wave_lds_sync();
+    }
+    for_each_tile<PERSIST>(P, [&](int t, const Ctx& Q) {
+        const int s = find_scene(Q.desc, t);
+        fwd_tile<CP, CKPT, STATS>(Q, s, t - Q.desc->s[s].tile_off, bm);
     });
 }
 
@@ -528,9 +654,9 @@ template <int CP, bool STATS>
 __global__ __launch_bounds__(256) void k_render_bwd(Ctx P) {
     extern __shared__ float smem[];   // [wave][3][K][64]
     float* sw = smem + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 3 * P.mr.K * 64;
-    for_each_tile<false>(P, [&](int t) {
-        const int s = find_scene(P.desc, t);
-        bwd_sm_tile<CP, STATS>(P, s, t - P.desc->s[s].tile_off, sw);
+    for_each_tile<false>(P, [&](int t, const Ctx& Q) {
+        const int s = find_scene(Q.desc, t);
+        bwd_sm_tile<CP, STATS>(Q, s, t - Q.desc->s[s].tile_off, sw);
     });
 }
 
@@ -554,40 +680,6 @@ __global__ __launch_bounds__(256) void k_render_bwd(Ctx P) {
 //     reductions and atomics shrink by the number of chunk samples that share
 //     a primitive.
 // ---------------------------------------------------------------------------
-constexpr int PV_BITS_X = 11, PV_BITS_Y = 11;    // packed voxel: ix | iy << 11 | iz << 22
-constexpr int KM_MAX_XY = (1 << 11) - 1, KM_MAX_Z = (1 << 9) - 1;
-
-__device__ __forceinline__ int pack_voxel(int ix, int iy, int iz) {
-    return ix | (iy << PV_BITS_X) | (iz << (PV_BITS_X + PV_BITS_Y));
-}
-
-// k listed in packed voxel pv (pv < 0: dead sample)?
-__device__ __forceinline__ bool listed_in(int pv, int bx, int by, int bz) {
-    const int ix = pv & ((1 << PV_BITS_X) - 1);
-    const int iy = (pv >> PV_BITS_X) & ((1 << PV_BITS_Y) - 1);
-    const int iz = (int)((unsigned)pv >> (PV_BITS_X + PV_BITS_Y));
-    return (pv >= 0) & in_range(ix, bx) & in_range(iy, by) & in_range(iz, bz);
-}
-
-// Visit the set bits of a per-wave bitmap in ascending order (wave-uniform).
-template <typename F>
-__device__ __forceinline__ void for_each_marked(const uint32_t* bm, int nw, int lane, F&& body) {
-    for (int wb = 0; wb < nw; wb += 64) {
-        const uint32_t word = bm[wb + lane];
-        uint64_t nz = wave_ballot(word != 0u);
-        while (nz) {
-            const int l = __builtin_ctzll(nz);
-            nz &= nz - 1;
-            uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)word, l);
-            while (wv) {
-                const int b = __builtin_ctz(wv);
-                wv &= wv - 1;
-                body(((wb + l) << 5) + b);
-            }
-        }
-    }
-}
-
 template <int CP, int KC, bool STATS>
 __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint32_t* bm) {
     const SceneDev& S = P.desc->s[s];
@@ -793,9 +885,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
     Ctx P) {
     extern __shared__ uint32_t bm_all[];
     uint32_t* bm = bm_all + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * P.bitmap_words;
-    for_each_tile<PERSIST>(P, [&](int t) {
-        const int s = find_scene(P.desc, t);
-        bwd_km_tile<CP, KC, STATS>(P, s, t - P.desc->s[s].tile_off, bm);
+    for_each_tile<PERSIST>(P, [&](int t, const Ctx& Q) {
+        const int s = find_scene(Q.desc, t);
+        bwd_km_tile<CP, KC, STATS>(Q, s, t - Q.desc->s[s].tile_off, bm);
     });
 }
 
@@ -976,24 +1068,32 @@ static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, co
     return P;
 }
 
+// LDS budget of the per-wave bitmaps of one block.
+static bool bitmap_fits(int max_n, int wpb) {
+    return (size_t)wpb * bitmap_words(max_n) * sizeof(uint32_t) <= 64 * 1024;
+}
+
 template <int CP>
-static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P,
+static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P0,
                     const TuneDev& t, hipStream_t st) {
     prep_records<CP>(d, g, io, l, st);
-    const bool ck = P.ckpt != nullptr, stt = P.stats != nullptr;
     const int wpb = t.waves_per_block;
+    Ctx P = P0;
+    if (!bitmap_fits(d.max_n, wpb)) P.bitmap_words = 0;
+    const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);
+    const bool ck = P.ckpt != nullptr, stt = P.stats != nullptr;
     if (stt) {
-        if (ck) launch_tiles(k_render_fwd<CP, true, true, false>, false, P, wpb, 0, st);
-        else launch_tiles(k_render_fwd<CP, false, true, false>, false, P, wpb, 0, st);
+        if (ck) launch_tiles(k_render_fwd<CP, true, true, false>, false, P, wpb, shm, st);
+        else launch_tiles(k_render_fwd<CP, false, true, false>, false, P, wpb, shm, st);
         return;
     }
     if (t.persistent) {
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, P.queue, N_XCD * QUEUE_STRIDE, 0);
-        if (ck) launch_tiles(k_render_fwd<CP, true, false, true>, true, P, wpb, 0, st);
-        else launch_tiles(k_render_fwd<CP, false, false, true>, true, P, wpb, 0, st);
+        if (ck) launch_tiles(k_render_fwd<CP, true, false, true>, true, P, wpb, shm, st);
+        else launch_tiles(k_render_fwd<CP, false, false, true>, true, P, wpb, shm, st);
     } else {
-        if (ck) launch_tiles(k_render_fwd<CP, true, false, false>, false, P, wpb, 0, st);
-        else launch_tiles(k_render_fwd<CP, false, false, false>, false, P, wpb, 0, st);
+        if (ck) launch_tiles(k_render_fwd<CP, true, false, false>, false, P, wpb, shm, st);
+        else launch_tiles(k_render_fwd<CP, false, false, false>, false, P, wpb, shm, st);
     }
 }
 
@@ -1017,7 +1117,7 @@ hipError_t launch_batch_fwd(const GridDev& g, const BatchDesc& d, const MarchDev
 bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb) {
     if (!(K == 4 || K == 8)) return false;
     if (g.X > KM_MAX_XY || g.Y > KM_MAX_XY || g.Z > KM_MAX_Z) return false;
-    return (size_t)wpb * bitmap_words(max_n) * sizeof(uint32_t) <= 64 * 1024;
+    return bitmap_fits(max_n, wpb);
 }
 
 template <int CP, int KC>
