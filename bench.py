@@ -90,7 +90,7 @@ def parse():
     ap.add_argument("--tile-w", type=int, default=8)
     ap.add_argument("--wpb", type=int, default=2)
     ap.add_argument("--bwd-mode", type=int, default=0, help="0 auto, 1 sample-major, 2 primitive-major")
-XX
+    ap.add_argument("--cpu-rays", type=int, default=32768, help="rays in the oracle's CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--autotune", action="store_true",

@@ -1,0 +1,28 @@
+"""bench.py's command line, on the CPU: the options parse, and a request for
+more than one GPU ends with a message and a non-zero status (this build runs
+on one GPU)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          timeout=120)
+
+
+def test_help_lists_the_options():
+    r = _run("--help")
+    assert r.returncode == 0, r.stderr
+    for opt in ("--gpus", "--steps", "--warmup", "--cpu-rays", "--no-cpu", "--autotune", "--calib-copy-mb"):
+        assert opt in r.stdout, opt
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2", "--steps", "1", "--warmup", "0")
+    assert r.returncode != 0
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
