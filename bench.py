@@ -208,6 +208,18 @@ def main():
     torch.cuda.synchronize()
     t_plain = pe[0].elapsed_time(pe[1]) / args.steps
 
+    # voxelisation of each scene's grid (Eq. eq:voxelisation, tau = 0.05) from the same index
+    vox = [api.voxelise(grid, idx, p, tau=0.05) for p, r, idx, out in plain]
+    torch.cuda.synchronize()
+    ve = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ve[0].record()
+    for _ in range(args.steps):
+        for (p, r, idx, out), vo in zip(plain, vox):
+            api.voxelise(grid, idx, p, tau=0.05, out=vo)
+    ve[1].record()
+    torch.cuda.synchronize()
+    t_vox = ve[0].elapsed_time(ve[1]) / args.steps
+
     workload = (f"config {args.config}: {len(scenes)} scene(s), {sum(s.prims.n for s in scenes)} superquadrics "
                 f"({'/'.join(str(s.prims.n) for s in scenes)}), {sc0.rays.shape[0]} cameras x "
                 f"{sc0.rays.shape[2]}x{sc0.rays.shape[1]} rays per scene, L={Ls} in [{sc0.march.t_near}, "
@@ -237,6 +249,9 @@ def main():
         "rays_per_s_fwd_bwd": R / (ms_step / 1e3),
         "index_ms": t_idx, "fwd_ms": t_fwd, "bwd_ms": t_bwd, "plain_fwd_ms": t_plain,
         "index_entries": sum(E),
+        "voxelise_ms": t_vox,
+        "voxelise_voxels_per_s": len(scenes) * grid.n_voxels / (t_vox / 1e3),
+        "voxelise_pairs_per_s": sum(E) / (t_vox / 1e3),
     }
     if tuned_ms is not None:
         result["autotune_ms"] = [round(m, 3) for m in tuned_ms]

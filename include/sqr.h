@@ -218,6 +218,25 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
                         const sq_grads* grads, int64_t* stats, const sq_tuning* tuning,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Bytes of workspace sq_voxelise needs (host-only). */
+size_t sq_voxelise_workspace(const sq_grid* grid, const sq_prims* prims);
+
+/* Superquadric voxelisation (Supplement "SuperQuadric Voxelisation",
+ * Eq. eq:voxelisation).  For every voxel v of the grid, with centre
+ *   p = fl(lo + fl(fl(i + 0.5) * voxel)) per axis (float32, no FMA),
+ * over the primitives listed in v (the same N_v lists as the render):
+ *   density[v]  = sum_k p_o(p, S_k) sigma_k
+ *   sem[c][v]   = sum_k p_o(p, S_k) c_k[c]
+ *   labels[v]   = n_classes ("free") where density[v] < tau, otherwise the
+ *                 smallest c with the largest sem[c][v] (compared in float32).
+ * The paper uses tau = 0.05.  Outputs: density [V] (required), sem [C, V]
+ * (nullable, class planes), labels [V] int32 (nullable), V = voxels in the
+ * linear order of sq_grid.  Same cull as sq_render_fwd.  Deterministic: each
+ * voxel sums its own list in ascending id. */
+sq_status sq_voxelise(const sq_grid* grid, const sq_index* idx, const sq_prims* prims, float tau,
+                      float* density, float* sem, int32_t* labels,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: several scenes that share one grid, one ray march and one
  * class count, with uneven primitive and camera counts, rendered by single
@@ -247,7 +266,9 @@ typedef struct {
  *  [sum rays * C] (each scene [n_cams, C, H, W]; probs nullable); ckpt
  *  [ceil(L/K) * sum rays] (each scene [ceil(L/K), its rays]); g_depth, g_sem
  *  shaped like depth and sem (nullable = zero); g_* shaped like the
- *  parameters.  A call reads and writes only the members it needs. */
+ *  parameters; vox_density, vox_labels [n_scenes * V] and vox_sem
+ *  [n_scenes * C * V] (each scene as in sq_voxelise).  A call reads and
+ *  writes only the members it needs. */
 typedef struct {
     const float *means, *quats, *scales, *eps, *opacity, *logits;
     const float *origins, *dirs;
@@ -256,6 +277,8 @@ typedef struct {
     float *depth, *sem, *probs, *t_final, *ckpt;
     const float *g_depth, *g_sem;
     float *g_means, *g_quats, *g_scales, *g_eps, *g_opacity, *g_logits;
+    float *vox_density, *vox_sem;
+    int32_t *vox_labels;
 } sq_batch_io;
 
 /* Bytes of workspace every batched call needs (host-only; 0 on bad input). */
@@ -278,6 +301,13 @@ sq_status sq_batch_render_fwd(const sq_batch* batch, const sq_batch_io* io, int6
  * same chunk.  `stats` as for sq_render_bwd. */
 sq_status sq_batch_render_bwd(const sq_batch* batch, const sq_batch_io* io, int64_t* stats,
                               const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* sq_voxelise for every scene of the batch in one launch (Supplement
+ * "SuperQuadric Voxelisation"); needs the index (counts, offsets, ids) and the
+ * primitive parameters; writes vox_density and, when not NULL, vox_sem and
+ * vox_labels. */
+sq_status sq_batch_voxelise(const sq_batch* batch, const sq_batch_io* io, float tau,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One training step of the renderer: index, forward with checkpoints,
  * backward (every output of io is written). */

@@ -12,9 +12,9 @@ takes part at voxel v exactly when v lies in the clipped cube of half-width
 N_v around the voxel containing m_i, i.e. when i is listed in V_sq(v).
 
 Readings (listed with the others in the design notes):
-R11 Voxel centres are float32, per axis p = fl(lo + fl(fl(i + 0.5) * voxel))
+R18 Voxel centres are float32, per axis p = fl(lo + fl(fl(i + 0.5) * voxel))
     (each op correctly rounded, no FMA); the evaluation downstream is FP64.
-R12 The final prediction is the class index argmax_c v_s (first maximum)
+R19 The final prediction is the class index argmax_c v_s (first maximum)
     where v_d >= tau, and the label n_classes ("free") where v_d < tau.
 """
 from __future__ import annotations
@@ -27,7 +27,7 @@ __all__ = ["voxel_centres", "voxelise", "labels_from"]
 
 
 def voxel_centres(grid):
-    """Per-axis FP32 voxel centres (reading R11): three arrays of length dims[a]."""
+    """Per-axis FP32 voxel centres (reading R18): three arrays of length dims[a]."""
     out = []
     for a in range(3):
         i = np.arange(grid.dims[a]).astype(F32)
@@ -42,7 +42,7 @@ def _voxel_coords(grid, v):
 
 
 def labels_from(density, sem, tau):
-    """Reading R12: class argmax (first maximum) where density >= tau, else C."""
+    """Reading R19: class argmax (first maximum) where density >= tau, else C."""
     C = sem.shape[-1]
     lab = np.argmax(sem, axis=-1).astype(np.int64)
     return np.where(density < tau, C, lab)

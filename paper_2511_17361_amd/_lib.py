@@ -24,6 +24,7 @@ EXPORTED = [
     "sq_build_index_workspace", "sq_build_index", "sq_render_workspace", "sq_render_fwd", "sq_render_bwd",
     "sq_batch_workspace", "sq_batch_build_index", "sq_batch_render_fwd", "sq_batch_render_bwd", "sq_batch_step",
     "sq_batch_step_graph_create", "sq_graph_launch", "sq_graph_destroy", "sq_batch_autotune",
+    "sq_voxelise_workspace", "sq_voxelise", "sq_batch_voxelise",
 ]
 
 
@@ -83,7 +84,8 @@ class SqBatchIO(ct.Structure):
     _fields_ = [(n, ct.c_void_p) for n in (
         "means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs",
         "counts", "offsets", "ids", "totals", "depth", "sem", "probs", "t_final", "ckpt",
-        "g_depth", "g_sem", "g_means", "g_quats", "g_scales", "g_eps", "g_opacity", "g_logits")]
+        "g_depth", "g_sem", "g_means", "g_quats", "g_scales", "g_eps", "g_opacity", "g_logits",
+        "vox_density", "vox_sem", "vox_labels")]
 
 
 _lib = None
@@ -137,6 +139,13 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.sq_batch_autotune.restype = ct.c_int32
     lib.sq_batch_autotune.argtypes = [P(SqBatch), P(SqBatchIO), P(SqTuning), ct.c_int32, ct.c_int32,
                                       P(ct.c_int32), P(ct.c_float), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_voxelise_workspace.restype = ct.c_size_t
+    lib.sq_voxelise_workspace.argtypes = [P(SqGrid), P(SqPrims)]
+    lib.sq_voxelise.restype = ct.c_int32
+    lib.sq_voxelise.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), ct.c_float, ct.c_void_p, ct.c_void_p,
+                                ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_batch_voxelise.restype = ct.c_int32
+    lib.sq_batch_voxelise.argtypes = [P(SqBatch), P(SqBatchIO), ct.c_float, ct.c_void_p, ct.c_size_t, ct.c_void_p]
     _lib = lib
     return lib
 

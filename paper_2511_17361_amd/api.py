@@ -296,7 +296,31 @@ def render_bwd_stats(grid, index: Index, prims: Prims, rays: Rays, march, ckpt, 
 
 _IO_FIELDS = ("means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs", "counts", "offsets", "ids",
               "totals", "depth", "sem", "probs", "t_final", "ckpt", "g_depth", "g_sem", "g_means", "g_quats",
-              "g_scales", "g_eps", "g_opacity", "g_logits")
+              "g_scales", "g_eps", "g_opacity", "g_logits", "vox_density", "vox_sem", "vox_labels")
+
+
+def voxelise(grid, index: Index, prims: Prims, tau: float = 0.05, sem: bool = True, labels: bool = True,
+             stream=None, ws: Optional[Workspace] = None, out: Optional[dict] = None) -> dict:
+    """sq_voxelise (Eq. eq:voxelisation).  Returns density [X,Y,Z], sem
+    [C,X,Y,Z] and labels [X,Y,Z] (int32, n_classes = free) on the device."""
+    lib = L.load()
+    grid = Grid.of(grid)
+    dev = prims.means.device
+    X, Y, Z = grid.dims
+    C = prims.n_classes
+    if out is None:
+        out = dict(density=torch.empty((X, Y, Z), device=dev))
+        if sem:
+            out["sem"] = torch.empty((C, X, Y, Z), device=dev)
+        if labels:
+            out["labels"] = torch.empty((X, Y, Z), dtype=torch.int32, device=dev)
+    g, p, ix = grid.c(), prims.c(), index.c()
+    need = lib.sq_voxelise_workspace(ct.byref(g), ct.byref(p))
+    wbuf = ws.get(need) if ws is not None else _workspace(need, dev)
+    L.check(lib.sq_voxelise(ct.byref(g), ct.byref(ix), ct.byref(p), ct.c_float(tau), _ptr(out["density"]),
+                            _ptr(out.get("sem")), _ptr(out.get("labels")), _ptr(wbuf), wbuf.numel(),
+                            _stream_handle(stream)))
+    return out
 
 
 class Batch:
@@ -385,6 +409,24 @@ class Batch:
         t = (tuning or Tuning()).c()
         self._call(lib.sq_batch_render_bwd, _ptr(stats), ct.byref(t), _ptr(self.ws), self.ws.numel(),
                    _stream_handle(stream))
+
+    def voxelise(self, tau: float = 0.05, stream=None):
+        """sq_batch_voxelise into vox_density [S*V], vox_sem [S*C*V], vox_labels [S*V]."""
+        lib = L.load()
+        if self.buf.get("vox_density") is None:
+            S, V, C = len(self.scene_shapes), self.grid.n_voxels, self.n_classes
+            self.buf["vox_density"] = torch.zeros(S * V, device=self.device)
+            self.buf["vox_sem"] = torch.zeros(S * C * V, device=self.device)
+            self.buf["vox_labels"] = torch.zeros(S * V, dtype=torch.int32, device=self.device)
+        self._call(lib.sq_batch_voxelise, ct.c_float(tau), _ptr(self.ws), self.ws.numel(), _stream_handle(stream))
+
+    def scene_voxels(self, i):
+        """Scene i's voxelisation outputs shaped [X,Y,Z] / [C,X,Y,Z]."""
+        V, C = self.grid.n_voxels, self.n_classes
+        X, Y, Z = self.grid.dims
+        return dict(density=self.buf["vox_density"][i * V:(i + 1) * V].view(X, Y, Z),
+                    sem=self.buf["vox_sem"][i * C * V:(i + 1) * C * V].view(C, X, Y, Z),
+                    labels=self.buf["vox_labels"][i * V:(i + 1) * V].view(X, Y, Z))
 
     def step(self, tuning: Optional[Tuning] = None, stream=None):
         lib = L.load()

@@ -55,6 +55,7 @@ sqr::GridDev to_dev(const sq_grid* g) {
     d.inv = 1.0f / g->voxel;   // fl32(1/voxel): x86 SSE division is correctly rounded
     d.X = g->dims[0]; d.Y = g->dims[1]; d.Z = g->dims[2];
     d.nv = g->nv;
+    d.vs = g->voxel;
     return d;
 }
 
@@ -191,6 +192,7 @@ sqr::BatchIO to_dev(const sq_batch_io* io) {
     b.g_depth = io->g_depth; b.g_sem = io->g_sem;
     b.g_means = io->g_means; b.g_quats = io->g_quats; b.g_scales = io->g_scales; b.g_eps = io->g_eps;
     b.g_opacity = io->g_opacity; b.g_logits = io->g_logits;
+    b.vox_density = io->vox_density; b.vox_sem = io->vox_sem; b.vox_labels = io->vox_labels;
     return b;
 }
 
@@ -238,6 +240,18 @@ sq_status bwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
     if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
     const hipError_t e = sqr::launch_batch_bwd(p.g, p.d, to_dev(&p.m, K), to_dev(io), stats, tune, ws, stream);
     return hip_status(e, "render_bwd");
+}
+
+sq_status vox_checked(const Plan& p, const sq_batch_io* io, float tau, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+    sq_status s;
+    if ((s = check_io_index(p, io))) return s;
+    if (p.d.total_prims > 0 && (!io->quats || !io->scales || !io->eps || !io->opacity || !io->logits))
+        return fail(SQ_ERR_INVALID, "a primitive parameter array is NULL");
+    if (!std::isfinite(tau)) return fail(SQ_ERR_INVALID, "tau must be finite");
+    if (!io->vox_density) return fail(SQ_ERR_INVALID, "density output is NULL");
+    if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+    return hip_status(sqr::launch_batch_voxelise(p.g, p.d, to_dev(io), tau, ws, stream), "voxelise");
 }
 
 // ---- single-scene adapters --------------------------------------------------
@@ -306,7 +320,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 200; }
+int32_t sq_version(void) { return 201; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
@@ -412,6 +426,26 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
     return bwd_checked(p, &io, stats, &t, ws, ws_bytes, stream);
 }
 
+size_t sq_voxelise_workspace(const sq_grid* grid, const sq_prims* prims) {
+    return sq_render_workspace(grid, prims, nullptr, nullptr);
+}
+
+sq_status sq_voxelise(const sq_grid* grid, const sq_index* idx, const sq_prims* prims, float tau, float* density,
+                      float* sem, int32_t* labels, void* ws, size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_grid(grid))) return s;
+    if ((s = check_index(idx, true))) return s;
+    if ((s = check_prims(prims, true))) return s;
+    sq_batch b;
+    one_scene(grid, &kIndexMarch, prims->n, prims->n_classes, 0, 0, 0, idx->capacity, b);
+    Plan p;
+    if ((s = make_plan(&b, 8, p))) return s;
+    sq_batch_io io;
+    io_from(idx, prims, nullptr, io);
+    io.vox_density = density; io.vox_sem = sem; io.vox_labels = labels;
+    return vox_checked(p, &io, tau, ws, ws_bytes, stream);
+}
+
 // ---- batched -------------------------------------------------------------------
 size_t sq_batch_workspace(const sq_batch* b) {
     Plan p;
@@ -435,6 +469,14 @@ sq_status sq_batch_render_fwd(const sq_batch* b, const sq_batch_io* io, int64_t*
     Plan p;
     if ((s = make_plan(b, tune.tile_w, p))) return s;
     return fwd_checked(p, io, stats, tuning, ws, ws_bytes, stream);
+}
+
+sq_status sq_batch_voxelise(const sq_batch* b, const sq_batch_io* io, float tau, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+    sq_status s;
+    Plan p;
+    if ((s = make_plan(b, 8, p))) return s;
+    return vox_checked(p, io, tau, ws, ws_bytes, stream);
 }
 
 sq_status sq_batch_render_bwd(const sq_batch* b, const sq_batch_io* io, int64_t* stats, const sq_tuning* tuning,

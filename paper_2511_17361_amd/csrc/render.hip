@@ -66,6 +66,9 @@ struct Ctx {
     float* acc;
     int64_t* stats;
     int bitmap_words;           // per-wave union bitmap size (0: none)
+    float tau;                  // voxelisation: free-space density threshold
+    float *vox_density, *vox_sem;
+    int32_t* vox_labels;
 };
 
 // ---------------------------------------------------------------------------
@@ -480,6 +483,109 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP,
         const int s = find_scene(Q.desc, t);
         fwd_tile<CP, CKPT, STATS>(Q, s, t - Q.desc->s[s].tile_off, bm);
     });
+}
+
+// ---------------------------------------------------------------------------
+// Voxelisation (Supplement "SuperQuadric Voxelisation", Eq. eq:voxelisation)
+//
+// One wavefront per 4x4x4 block of voxels of one scene (blockIdx.y), one lane
+// per voxel.  The wave marks the union of its voxels' lists in its LDS bitmap
+// and walks it in ascending id; each lane takes the primitives whose box holds
+// its voxel -- its own list, in its own order -- and evaluates p_o at its
+// float32 voxel centre:  v_d = sum p sigma,  v_s = sum p c.  The label is the
+// first class maximising v_s, or C ("free") where v_d < tau.  Without a
+// bitmap (LDS budget exceeded) each lane walks its own list.
+// ---------------------------------------------------------------------------
+template <int CP>
+__global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
+    extern __shared__ uint32_t bm_all[];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* bm = nullptr;
+    if (P.bitmap_words > 0) {
+        bm = bm_all + (size_t)wave * P.bitmap_words;
+        for (int w = lane; w < P.bitmap_words; w += 64) bm[w] = 0u;
+        wave_lds_sync();
+    }
+    const int nbx = (P.g.X + 3) >> 2, nby = (P.g.Y + 3) >> 2, nbz = (P.g.Z + 3) >> 2;
+    const int blk = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (int)(blockDim.x >> 6) + wave);
+    if (blk >= nbx * nby * nbz) return;
+    const int s = blockIdx.y;
+    const SceneDev& S = P.desc->s[s];
+    const SceneIndex X = scene_index<CP>(P, s, S);
+    const int nw = ((X.n + 31) / 32 + 63) / 64 * 64;
+    const int bz = blk % nbz, by = (blk / nbz) % nby, bx = blk / (nbz * nby);
+    const int ix = 4 * bx + (lane >> 4), iy = 4 * by + ((lane >> 2) & 3), iz = 4 * bz + (lane & 3);
+    const bool valid = (ix < P.g.X) & (iy < P.g.Y) & (iz < P.g.Z);
+    const int v = valid ? (ix * P.g.Y + iy) * P.g.Z + iz : 0;
+    int n = 0, f = 0;
+    if (valid) { n = X.counts[v]; f = X.offsets[v]; }
+    const bool act = valid && n > 0;
+    const float cx = pinned_voxel_centre(P.g.lox, P.g.vs, ix);
+    const float cy = pinned_voxel_centre(P.g.loy, P.g.vs, iy);
+    const float cz = pinned_voxel_centre(P.g.loz, P.g.vs, iz);
+
+    float d = 0.0f;
+    float sv[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
+    auto add_pair = [&](int k) {
+        const cf_ptr r = X.rec + (size_t)k * REC;
+        const float p = eval_p(r, cx, cy, cz);
+        if (p != 0.0f) {
+            d = fmaf(p, r[15], d);
+            const cf_ptr lg = X.lgp + (size_t)k * CP;
+#pragma unroll
+            for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
+        }
+    };
+    uint64_t m = wave_ballot(act);
+    if (m != 0 && bm) {
+        while (m) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            const int f0 = readlane_i(f, l);
+            const int n0 = clamp_list(f0, readlane_i(n, l), X.cap);
+            for (int e = lane; e < n0; e += 64) {
+                const int k = X.ids[f0 + e];
+                if ((unsigned)k < (unsigned)X.n) atomicOr(&bm[k >> 5], 1u << (k & 31));
+            }
+        }
+        wave_lds_sync();
+        for_each_marked<true>(bm, nw, lane, [&](int k) {
+            const cf_ptr r = X.rec + (size_t)k * REC;
+            const bool mem = act && in_range(ix, __float_as_int(r[20])) && in_range(iy, __float_as_int(r[21])) &&
+                             in_range(iz, __float_as_int(r[22]));
+            if (mem) add_pair(k);
+        });
+    } else if (act) {
+        const int n0 = clamp_list(f, n, X.cap);
+        for (int e = 0; e < n0; ++e) {
+            const int k = P.ids[S.ids_base + f + e];
+            if ((unsigned)k < (unsigned)X.n) add_pair(k);
+        }
+    }
+    if (valid) {
+        const int64_t nvox = (int64_t)P.g.X * P.g.Y * P.g.Z;
+        const int64_t vo = (int64_t)s * nvox + v;
+        P.vox_density[vo] = d;
+        if (P.vox_sem) {
+#pragma unroll
+            for (int c = 0; c < CP; ++c)
+                if (c < P.C) P.vox_sem[((int64_t)s * P.C + c) * nvox + v] = sv[c];
+        }
+        if (P.vox_labels) {
+            int lab = P.C;
+            if (!(d < P.tau)) {
+                lab = 0;
+                float best = sv[0];
+#pragma unroll
+                for (int c = 1; c < CP; ++c)
+                    if (c < P.C && sv[c] > best) { best = sv[c]; lab = c; }
+            }
+            P.vox_labels[vo] = lab;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1065,6 +1171,8 @@ static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, co
     P.depth = io.depth; P.sem = io.sem; P.probs = io.probs; P.t_final = io.t_final; P.ckpt = io.ckpt;
     P.g_depth = io.g_depth; P.g_sem = io.g_sem; P.acc = l.acc; P.stats = stats;
     P.bitmap_words = bitmap_words(d.max_n);
+    P.tau = 0.0f;
+    P.vox_density = io.vox_density; P.vox_sem = io.vox_sem; P.vox_labels = io.vox_labels;
     return P;
 }
 
@@ -1107,6 +1215,37 @@ hipError_t launch_batch_fwd(const GridDev& g, const BatchDesc& d, const MarchDev
         case 8: fwd_run<8>(g, d, io, l, P, tune, st); break;
         case 17: fwd_run<17>(g, d, io, l, P, tune, st); break;
         default: fwd_run<32>(g, d, io, l, P, tune, st); break;
+    }
+    return hipGetLastError();
+}
+
+template <int CP>
+static void vox_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P0,
+                    hipStream_t st) {
+    prep_records<CP>(d, g, io, l, st);
+    int wpb = 4;
+    while (wpb > 1 && !bitmap_fits(d.max_n, wpb)) wpb /= 2;
+    Ctx P = P0;
+    if (!bitmap_fits(d.max_n, wpb)) P.bitmap_words = 0;
+    const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);
+    const int64_t nblk = (int64_t)((g.X + 3) / 4) * ((g.Y + 3) / 4) * ((g.Z + 3) / 4);
+    const dim3 grid((unsigned)((nblk + wpb - 1) / wpb), (unsigned)d.n_scenes);
+    hipLaunchKernelGGL(k_voxelise<CP>, grid, dim3(64 * wpb), shm, st, P);
+}
+
+hipError_t launch_batch_voxelise(const GridDev& g, const BatchDesc& d, const BatchIO& io, float tau, void* ws,
+                                 hipStream_t st) {
+    const WsLayout l = carve_ws(ws, g, d);
+    put_desc(d, l.desc, st);
+    MarchDev mr;
+    mr.L = 1; mr.t_near = 0.0f; mr.delta = 0.0f; mr.K = 0;
+    Ctx P = make_ctx(g, d, mr, io, l, nullptr);
+    P.tau = tau;
+    switch (padded_classes(d.C)) {
+        case 4: vox_run<4>(g, d, io, l, P, st); break;
+        case 8: vox_run<8>(g, d, io, l, P, st); break;
+        case 17: vox_run<17>(g, d, io, l, P, st); break;
+        default: vox_run<32>(g, d, io, l, P, st); break;
     }
     return hipGetLastError();
 }

@@ -53,6 +53,7 @@ struct GridDev {
     float inv;          // fl(1/voxel), computed on the host
     int X, Y, Z;
     int nv;
+    float vs;           // voxel edge length
 };
 
 struct SamplePos {
@@ -81,6 +82,14 @@ __device__ __forceinline__ SamplePos pinned_sample(const GridDev& g, float t_nea
     s.iz = in ? (int)qz : 0;
     s.v = in ? ((s.ix * g.Y + s.iy) * g.Z + s.iz) : -1;
     return s;
+}
+
+// Centre of voxel i along one axis in float32, fl(lo + fl(fl(i + 0.5) * voxel))
+// with no fused multiply-add (the point the voxelisation evaluates).
+__device__ __forceinline__ float pinned_voxel_centre(float lo, float vs, int i) {
+#pragma clang fp contract(off)
+    const float h = (float)i + 0.5f;
+    return lo + h * vs;
 }
 
 // Centre voxel of a primitive along one axis, bounded before conversion.

@@ -66,6 +66,8 @@ struct BatchIO {
     float *depth, *sem, *probs, *t_final, *ckpt;
     const float *g_depth, *g_sem;
     float *g_means, *g_quats, *g_scales, *g_eps, *g_opacity, *g_logits;
+    float *vox_density, *vox_sem;
+    int32_t* vox_labels;
 };
 
 // class count padded to the compiled widths
@@ -83,6 +85,9 @@ hipError_t launch_batch_fwd(const GridDev& g, const BatchDesc& d, const MarchDev
                             int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
 hipError_t launch_batch_bwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
                             int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
+
+hipError_t launch_batch_voxelise(const GridDev& g, const BatchDesc& d, const BatchIO& io, float tau, void* ws,
+                                 hipStream_t st);
 
 // whether the primitive-major backward applies to these arguments
 bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb);

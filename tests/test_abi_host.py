@@ -148,3 +148,99 @@ def test_build_index_rejects_bad_arguments():
     i = _index()
     rc = lib.sq_build_index(ct.byref(big), ct.byref(p), ct.byref(i), 0x100000, 1 << 30, None)
     assert rc == L.SQ_ERR_INVALID
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda a: a.__setitem__("tau", float("nan")), L.SQ_ERR_INVALID),
+    (lambda a: a.__setitem__("tau", float("inf")), L.SQ_ERR_INVALID),
+    (lambda a: a.__setitem__("density", None), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["prims"], "opacity", None), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["prims"], "n_classes", 0), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["index"], "offsets", None), L.SQ_ERR_INVALID),
+    (lambda a: setattr(a["grid"], "voxel", -0.4), L.SQ_ERR_INVALID),
+    (lambda a: a.__setitem__("ws_bytes", 64), L.SQ_ERR_CAPACITY),
+    (lambda a: a.__setitem__("ws", 0x100010), L.SQ_ERR_INVALID),
+])
+def test_voxelise_rejects_bad_arguments_without_launch(mutate, code):
+    lib = L.load()
+    args = dict(grid=_grid(), prims=_prims(), index=_index(), tau=0.05, density=FAKE, ws=0x100000, ws_bytes=1 << 30)
+    mutate(args)
+    rc = lib.sq_voxelise(ct.byref(args["grid"]), ct.byref(args["index"]), ct.byref(args["prims"]), args["tau"],
+                         args["density"], None, None, args["ws"], args["ws_bytes"], None)
+    assert rc == code
+    assert lib.sq_last_error().decode()
+
+
+def test_voxelise_workspace_matches_render_records():
+    lib = L.load()
+    g, p = _grid(), _prims(n=25600)
+    need = lib.sq_voxelise_workspace(ct.byref(g), ct.byref(p))
+    assert need >= 25600 * (24 + 17) * 4
+    bad = _prims(C=40)
+    assert lib.sq_voxelise_workspace(ct.byref(g), ct.byref(bad)) == 0
+
+
+def _batch(n_scenes=3, C=5):
+    b = L.SqBatch()
+    b.n_scenes, b.n_classes = n_scenes, C
+    b.grid = _grid()
+    b.march = _march(K=4)
+    for i in range(n_scenes):
+        b.scenes[i].n_prims = 10 * (i + 1)
+        b.scenes[i].n_cams, b.scenes[i].height, b.scenes[i].width = 2, 9, 13
+        b.scenes[i].index_capacity = 1000
+    return b
+
+
+def _batch_io():
+    io = L.SqBatchIO()
+    for name, _ in L.SqBatchIO._fields_:
+        setattr(io, name, FAKE)
+    return io
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda b, io: setattr(b, "n_scenes", 0), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(b, "n_scenes", 33), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(b, "n_classes", 0), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(b.scenes[1], "n_prims", -1), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(b.scenes[2], "width", -3), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(b.scenes[0], "index_capacity", -1), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(b.march, "n_samples", 0), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(io, "counts", None), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(io, "ids", None), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(io, "logits", None), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(io, "origins", None), L.SQ_ERR_INVALID),
+    (lambda b, io: setattr(io, "depth", None), L.SQ_ERR_INVALID),
+])
+def test_batch_forward_rejects_bad_arguments_without_launch(mutate, code):
+    lib = L.load()
+    b, io = _batch(), _batch_io()
+    mutate(b, io)
+    io.ckpt = None
+    t = L.SqTuning(8, 4, 0, 0, 0)
+    rc = lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30, None)
+    assert rc == code
+    assert lib.sq_last_error().decode()
+
+
+def test_batch_calls_reject_bad_tuning_chunk_and_workspace():
+    lib = L.load()
+    b, io = _batch(), _batch_io()
+    for t in (L.SqTuning(5, 4, 0, 0, 0), L.SqTuning(8, 0, 0, 0, 0), L.SqTuning(8, 4, 3, 0, 0),
+              L.SqTuning(8, 4, 0, 2, 0), L.SqTuning(8, 4, 0, 0, -1)):
+        assert lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30,
+                                       None) == L.SQ_ERR_INVALID
+    t = L.SqTuning(8, 4, 0, 0, 3)
+    assert lib.sq_batch_render_bwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30,
+                                   None) == L.SQ_ERR_INVALID
+    t = L.SqTuning(8, 4, 0, 0, 4)
+    assert lib.sq_batch_step(ct.byref(b), ct.byref(io), ct.byref(t), 0x100000, 256, None) == L.SQ_ERR_CAPACITY
+    need = lib.sq_batch_workspace(ct.byref(b))
+    assert need > 0
+    assert lib.sq_batch_voxelise(ct.byref(b), ct.byref(io), float("nan"), 0x100000, need, None) == L.SQ_ERR_INVALID
+    io.vox_density = None
+    assert lib.sq_batch_voxelise(ct.byref(b), ct.byref(io), 0.05, 0x100000, need, None) == L.SQ_ERR_INVALID
+    bad = _batch()
+    bad.n_scenes = 40
+    assert lib.sq_batch_workspace(ct.byref(bad)) == 0
