@@ -218,6 +218,34 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
                         const sq_grads* grads, int64_t* stats, const sq_tuning* tuning,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Weights of the training loss of Eq. eq:loss (Supplement "Loss
+ * Formulation"): L = lambda_sem * L_sem + lambda_depth * L_depth; the paper
+ * uses lambda_sem = 2, lambda_depth = 0.05. */
+typedef struct {
+    float lambda_sem;
+    float lambda_depth;
+} sq_loss_weights;
+
+/* sq_render_fwd with the loss of Eq. eq:loss fused into the forward's
+ * epilogue.  Per pixel, against the pseudo-labels sem_label [n_cams,H,W]
+ * (int32 class; outside [0, C) = no label) and depth_label [n_cams,H,W]
+ * (metres; a label counts where it is finite and > 0):
+ *   L_sem   = mean over labelled pixels of -log softmax(sem)[label]
+ *   L_depth = mean over labelled pixels of (depth - depth_label)^2
+ * It writes (besides every output of sq_render_fwd) the upstream gradients
+ *   g_sem   [n_cams,C,H,W] = lambda_sem / N_sem * (softmax(sem) - onehot(label))
+ *   g_depth [n_cams,H,W]   = lambda_depth / N_depth * 2 (depth - depth_label)
+ * (zero on unlabelled pixels) that sq_render_bwd consumes, and
+ * loss[0..2] = (L, L_sem, L_depth), reduced in a fixed order (deterministic;
+ * a term with no labelled pixel is 0).  Labelled pixels are counted by the
+ * same call before the render. */
+sq_status sq_render_fwd_loss(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
+                             const sq_rays* rays, const sq_march* march, const sq_loss_weights* weights,
+                             const int32_t* sem_label, const float* depth_label,
+                             float* depth, float* sem, float* probs, float* t_final, float* ckpt,
+                             float* g_depth, float* g_sem, float* loss, const sq_tuning* tuning,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Bytes of workspace sq_voxelise needs (host-only). */
 size_t sq_voxelise_workspace(const sq_grid* grid, const sq_prims* prims);
 
@@ -267,8 +295,10 @@ typedef struct {
  *  [ceil(L/K) * sum rays] (each scene [ceil(L/K), its rays]); g_depth, g_sem
  *  shaped like depth and sem (nullable = zero); g_* shaped like the
  *  parameters; vox_density, vox_labels [n_scenes * V] and vox_sem
- *  [n_scenes * C * V] (each scene as in sq_voxelise).  A call reads and
- *  writes only the members it needs. */
+ *  [n_scenes * C * V] (each scene as in sq_voxelise); sem_label,
+ *  depth_label shaped like depth (pseudo-labels of the fused loss) and loss
+ *  (3 floats).  The fused-loss calls WRITE the buffers g_depth and g_sem
+ *  point to.  A call reads and writes only the members it needs. */
 typedef struct {
     const float *means, *quats, *scales, *eps, *opacity, *logits;
     const float *origins, *dirs;
@@ -279,6 +309,9 @@ typedef struct {
     float *g_means, *g_quats, *g_scales, *g_eps, *g_opacity, *g_logits;
     float *vox_density, *vox_sem;
     int32_t *vox_labels;
+    const int32_t *sem_label;
+    const float *depth_label;
+    float *loss;
 } sq_batch_io;
 
 /* Bytes of workspace every batched call needs (host-only; 0 on bad input). */
@@ -302,6 +335,11 @@ sq_status sq_batch_render_fwd(const sq_batch* batch, const sq_batch_io* io, int6
 sq_status sq_batch_render_bwd(const sq_batch* batch, const sq_batch_io* io, int64_t* stats,
                               const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* sq_render_fwd_loss for every scene of the batch: the means of Eq. eq:loss
+ * run over the labelled pixels of all scenes together. */
+sq_status sq_batch_render_fwd_loss(const sq_batch* batch, const sq_batch_io* io, const sq_loss_weights* weights,
+                                   const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* sq_voxelise for every scene of the batch in one launch (Supplement
  * "SuperQuadric Voxelisation"); needs the index (counts, offsets, ids) and the
  * primitive parameters; writes vox_density and, when not NULL, vox_sem and
@@ -314,6 +352,11 @@ sq_status sq_batch_voxelise(const sq_batch* batch, const sq_batch_io* io, float 
 sq_status sq_batch_step(const sq_batch* batch, const sq_batch_io* io, const sq_tuning* tuning,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* One training step with the fused loss: index, forward with checkpoints and
+ * the loss epilogue (writing g_depth, g_sem and loss), backward. */
+sq_status sq_batch_train_step(const sq_batch* batch, const sq_batch_io* io, const sq_loss_weights* weights,
+                              const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Captures sq_batch_step on `stream` (not the legacy default stream) into a
  * hipGraph and instantiates it.  The graph keeps every pointer of io and ws:
  * replays read the current contents of the same buffers.  The step contains
@@ -321,6 +364,10 @@ sq_status sq_batch_step(const sq_batch* batch, const sq_batch_io* io, const sq_t
 typedef struct sq_graph_impl* sq_graph;
 sq_status sq_batch_step_graph_create(const sq_batch* batch, const sq_batch_io* io, const sq_tuning* tuning,
                                      void* ws, size_t ws_bytes, hipStream_t stream, sq_graph* out);
+/* The same for sq_batch_train_step. */
+sq_status sq_batch_train_graph_create(const sq_batch* batch, const sq_batch_io* io, const sq_loss_weights* weights,
+                                      const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream,
+                                      sq_graph* out);
 sq_status sq_graph_launch(sq_graph graph, hipStream_t stream);
 sq_status sq_graph_destroy(sq_graph graph);
 

@@ -25,6 +25,7 @@ EXPORTED = [
     "sq_batch_workspace", "sq_batch_build_index", "sq_batch_render_fwd", "sq_batch_render_bwd", "sq_batch_step",
     "sq_batch_step_graph_create", "sq_graph_launch", "sq_graph_destroy", "sq_batch_autotune",
     "sq_voxelise_workspace", "sq_voxelise", "sq_batch_voxelise",
+    "sq_render_fwd_loss", "sq_batch_render_fwd_loss", "sq_batch_train_step", "sq_batch_train_graph_create",
 ]
 
 
@@ -85,7 +86,11 @@ class SqBatchIO(ct.Structure):
         "means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs",
         "counts", "offsets", "ids", "totals", "depth", "sem", "probs", "t_final", "ckpt",
         "g_depth", "g_sem", "g_means", "g_quats", "g_scales", "g_eps", "g_opacity", "g_logits",
-        "vox_density", "vox_sem", "vox_labels")]
+        "vox_density", "vox_sem", "vox_labels", "sem_label", "depth_label", "loss")]
+
+
+class SqLossWeights(ct.Structure):
+    _fields_ = [("lambda_sem", ct.c_float), ("lambda_depth", ct.c_float)]
 
 
 _lib = None
@@ -146,6 +151,18 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                 ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]
     lib.sq_batch_voxelise.restype = ct.c_int32
     lib.sq_batch_voxelise.argtypes = [P(SqBatch), P(SqBatchIO), ct.c_float, ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_render_fwd_loss.restype = ct.c_int32
+    lib.sq_render_fwd_loss.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch), P(SqLossWeights),
+                                       ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                       ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, P(SqTuning), ct.c_void_p,
+                                       ct.c_size_t, ct.c_void_p]
+    for fn in (lib.sq_batch_render_fwd_loss, lib.sq_batch_train_step):
+        fn.restype = ct.c_int32
+        fn.argtypes = [P(SqBatch), P(SqBatchIO), P(SqLossWeights), P(SqTuning), ct.c_void_p, ct.c_size_t,
+                       ct.c_void_p]
+    lib.sq_batch_train_graph_create.restype = ct.c_int32
+    lib.sq_batch_train_graph_create.argtypes = [P(SqBatch), P(SqBatchIO), P(SqLossWeights), P(SqTuning),
+                                                ct.c_void_p, ct.c_size_t, ct.c_void_p, P(ct.c_void_p)]
     _lib = lib
     return lib
 

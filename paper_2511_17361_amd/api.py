@@ -296,7 +296,63 @@ def render_bwd_stats(grid, index: Index, prims: Prims, rays: Rays, march, ckpt, 
 
 _IO_FIELDS = ("means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs", "counts", "offsets", "ids",
               "totals", "depth", "sem", "probs", "t_final", "ckpt", "g_depth", "g_sem", "g_means", "g_quats",
-              "g_scales", "g_eps", "g_opacity", "g_logits", "vox_density", "vox_sem", "vox_labels")
+              "g_scales", "g_eps", "g_opacity", "g_logits", "vox_density", "vox_sem", "vox_labels", "sem_label",
+              "depth_label", "loss")
+
+# Loss weights of the paper (Supplement "Loss Formulation"): lambda_s = 2, lambda_d = 0.05.
+PAPER_LOSS = (2.0, 0.05)
+
+
+def _weights(loss) -> L.SqLossWeights:
+    w = L.SqLossWeights()
+    w.lambda_sem, w.lambda_depth = (float(loss[0]), float(loss[1]))
+    return w
+
+
+def _fwd_outputs(grid, prims, rays, march, ckpt_every, probs):
+    dev = prims.means.device
+    cams, H, W = rays.shape
+    C = prims.n_classes
+    out = dict(depth=torch.empty((cams, H, W), device=dev), sem=torch.empty((cams, C, H, W), device=dev),
+               t_final=torch.empty((cams, H, W), device=dev), g_depth=torch.empty((cams, H, W), device=dev),
+               g_sem=torch.empty((cams, C, H, W), device=dev), loss=torch.zeros(3, device=dev))
+    if probs:
+        out["probs"] = torch.empty((cams, C, H, W), device=dev)
+    if ckpt_every > 0:
+        out["ckpt"] = torch.empty((-(-march.n_samples // ckpt_every), cams * H * W), device=dev)
+    return out
+
+
+def render_fwd_loss(grid, index: Index, prims: Prims, rays: Rays, march, sem_label: torch.Tensor,
+                    depth_label: torch.Tensor, loss=PAPER_LOSS, ckpt_every: int = 0, probs: bool = True,
+                    tuning: Optional[Tuning] = None, stream=None, ws: Optional[Workspace] = None,
+                    out: Optional[dict] = None) -> dict:
+    """sq_render_fwd_loss: render_fwd plus the fused loss of Eq. eq:loss.
+    sem_label int32 [cams,H,W] (outside [0,C) = no label), depth_label
+    [cams,H,W] (> 0 = labelled).  Adds g_depth, g_sem (the upstream gradients
+    for render_bwd) and loss (3 floats: total, semantic, depth) to the outputs."""
+    lib = L.load()
+    grid, march = Grid.of(grid), March.of(march)
+    dev = prims.means.device
+    cams, H, W = rays.shape
+    C = prims.n_classes
+    if out is None:
+        out = _fwd_outputs(grid, prims, rays, march, ckpt_every, probs)
+    if sem_label.dtype != torch.int32 or not sem_label.is_contiguous():
+        raise ValueError("sem_label must be contiguous int32")
+    depth_label = _f32(depth_label, "depth_label")
+    g, p, r, m = grid.c(), prims.c(), rays.c(), march.c(ckpt_every)
+    ix = index.c()
+    t = (tuning or Tuning()).c()
+    w = _weights(loss)
+    need = lib.sq_render_workspace(ct.byref(g), ct.byref(p), ct.byref(r), ct.byref(m))
+    wbuf = ws.get(need) if ws is not None else _workspace(need, dev)
+    L.check(lib.sq_render_fwd_loss(ct.byref(g), ct.byref(ix), ct.byref(p), ct.byref(r), ct.byref(m), ct.byref(w),
+                                   _ptr(sem_label), _ptr(depth_label), _ptr(out["depth"]), _ptr(out["sem"]),
+                                   _ptr(out.get("probs")), _ptr(out["t_final"]), _ptr(out.get("ckpt")),
+                                   _ptr(out["g_depth"]), _ptr(out["g_sem"]), _ptr(out["loss"]), ct.byref(t),
+                                   _ptr(wbuf), wbuf.numel(), _stream_handle(stream)))
+    return out
 
 
 def voxelise(grid, index: Index, prims: Prims, tau: float = 0.05, sem: bool = True, labels: bool = True,
@@ -428,21 +484,52 @@ class Batch:
                     sem=self.buf["vox_sem"][i * C * V:(i + 1) * C * V].view(C, X, Y, Z),
                     labels=self.buf["vox_labels"][i * V:(i + 1) * V].view(X, Y, Z))
 
+    def set_labels(self, i, sem_label, depth_label):
+        """Scene i's pseudo-labels for the fused loss: sem_label int32 and
+        depth_label float, each [cams, H, W]."""
+        if self.buf.get("sem_label") is None:
+            R = self.n_rays
+            self.buf["sem_label"] = torch.full((R,), -1, dtype=torch.int32, device=self.device)
+            self.buf["depth_label"] = torch.zeros(R, device=self.device)
+            self.buf["loss"] = torch.zeros(3, device=self.device)
+        n0, n, r0, cams, H, W = self.scene_slices(i)
+        R = cams * H * W
+        self.buf["sem_label"][r0:r0 + R] = sem_label.reshape(-1).to(torch.int32)
+        self.buf["depth_label"][r0:r0 + R] = depth_label.reshape(-1)
+
+    def render_fwd_loss(self, loss=PAPER_LOSS, tuning: Optional[Tuning] = None, stream=None):
+        lib = L.load()
+        t = (tuning or Tuning()).c()
+        self._call(lib.sq_batch_render_fwd_loss, ct.byref(_weights(loss)), ct.byref(t), _ptr(self.ws),
+                   self.ws.numel(), _stream_handle(stream))
+
+    def train_step(self, loss=PAPER_LOSS, tuning: Optional[Tuning] = None, stream=None):
+        lib = L.load()
+        t = (tuning or Tuning()).c()
+        self._call(lib.sq_batch_train_step, ct.byref(_weights(loss)), ct.byref(t), _ptr(self.ws),
+                   self.ws.numel(), _stream_handle(stream))
+
     def step(self, tuning: Optional[Tuning] = None, stream=None):
         lib = L.load()
         t = (tuning or Tuning()).c()
         self._call(lib.sq_batch_step, ct.byref(t), _ptr(self.ws), self.ws.numel(), _stream_handle(stream))
 
-    def capture(self, tuning: Optional[Tuning] = None, stream=None):
-        """Capture one step into a hipGraph on `stream` (a non-default torch stream)."""
+    def capture(self, tuning: Optional[Tuning] = None, stream=None, loss=None):
+        """Capture one step into a hipGraph on `stream` (a non-default torch
+        stream); with `loss` weights, the training step with the fused loss."""
         lib = L.load()
         self.release_graph()
         t = (tuning or Tuning()).c()
         h = ct.c_void_p()
         stream = stream or torch.cuda.Stream(device=self.device)
-        L.check(lib.sq_batch_step_graph_create(ct.byref(self.c_batch), ct.byref(self.io()), ct.byref(t),
-                                               _ptr(self.ws), self.ws.numel(), _stream_handle(stream),
-                                               ct.byref(h)))
+        if loss is None:
+            L.check(lib.sq_batch_step_graph_create(ct.byref(self.c_batch), ct.byref(self.io()), ct.byref(t),
+                                                   _ptr(self.ws), self.ws.numel(), _stream_handle(stream),
+                                                   ct.byref(h)))
+        else:
+            L.check(lib.sq_batch_train_graph_create(ct.byref(self.c_batch), ct.byref(self.io()),
+                                                    ct.byref(_weights(loss)), ct.byref(t), _ptr(self.ws),
+                                                    self.ws.numel(), _stream_handle(stream), ct.byref(h)))
         self.graph = h
         self.graph_stream = stream
         return stream

@@ -193,6 +193,7 @@ sqr::BatchIO to_dev(const sq_batch_io* io) {
     b.g_means = io->g_means; b.g_quats = io->g_quats; b.g_scales = io->g_scales; b.g_eps = io->g_eps;
     b.g_opacity = io->g_opacity; b.g_logits = io->g_logits;
     b.vox_density = io->vox_density; b.vox_sem = io->vox_sem; b.vox_labels = io->vox_labels;
+    b.sem_label = io->sem_label; b.depth_label = io->depth_label; b.loss = io->loss;
     return b;
 }
 
@@ -240,6 +241,36 @@ sq_status bwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
     if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
     const hipError_t e = sqr::launch_batch_bwd(p.g, p.d, to_dev(&p.m, K), to_dev(io), stats, tune, ws, stream);
     return hip_status(e, "render_bwd");
+}
+
+sq_status check_loss(const Plan& p, const sq_batch_io* io, const sq_loss_weights* w) {
+    if (!w) return fail(SQ_ERR_INVALID, "loss weights are NULL");
+    if (!std::isfinite(w->lambda_sem) || !std::isfinite(w->lambda_depth))
+        return fail(SQ_ERR_INVALID, "loss weights must be finite");
+    if (!io->loss) return fail(SQ_ERR_INVALID, "loss output is NULL");
+    if (p.d.total_rays > 0 && (!io->sem_label || !io->depth_label))
+        return fail(SQ_ERR_INVALID, "semantic/depth labels are NULL");
+    if (p.d.total_rays > 0 && (!io->g_depth || !io->g_sem))
+        return fail(SQ_ERR_INVALID, "g_depth/g_sem (written by the fused loss) are NULL");
+    return SQ_OK;
+}
+
+sq_status fwd_loss_checked(const Plan& p, const sq_batch_io* io, const sq_loss_weights* w,
+                           const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_io_render(p, io))) return s;
+    if (p.d.total_rays > 0 && (!io->depth || !io->sem || !io->t_final))
+        return fail(SQ_ERR_INVALID, "depth/sem/t_final is NULL");
+    if ((s = check_loss(p, io, w))) return s;
+    const int K = chunk_of(tuning, p.m);
+    if (io->ckpt && K < 1) return fail(SQ_ERR_INVALID, "ckpt given but the checkpoint spacing is < 1");
+    sqr::TuneDev tune;
+    if ((s = tuning_of(tuning, tune))) return s;
+    if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+    const sqr::LossArgs la{w->lambda_sem, w->lambda_depth};
+    const hipError_t e = sqr::launch_batch_fwd(p.g, p.d, to_dev(&p.m, io->ckpt ? K : 0), to_dev(io), nullptr, tune,
+                                               ws, stream, &la);
+    return hip_status(e, "render_fwd_loss");
 }
 
 sq_status vox_checked(const Plan& p, const sq_batch_io* io, float tau, void* ws, size_t ws_bytes,
@@ -320,7 +351,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 201; }
+int32_t sq_version(void) { return 202; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
@@ -426,6 +457,33 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
     return bwd_checked(p, &io, stats, &t, ws, ws_bytes, stream);
 }
 
+sq_status sq_render_fwd_loss(const sq_grid* grid, const sq_index* idx, const sq_prims* prims, const sq_rays* rays,
+                             const sq_march* march, const sq_loss_weights* weights, const int32_t* sem_label,
+                             const float* depth_label, float* depth, float* sem, float* probs, float* t_final,
+                             float* ckpt, float* g_depth, float* g_sem, float* loss, const sq_tuning* tuning,
+                             void* ws, size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_grid(grid))) return s;
+    if ((s = check_index(idx, true))) return s;
+    if ((s = check_prims(prims, true))) return s;
+    if ((s = check_rays(rays))) return s;
+    if ((s = check_march(march))) return s;
+    sqr::TuneDev tune;
+    if ((s = tuning_of(tuning, tune))) return s;
+    if (ckpt && march->ckpt_every < 1) return fail(SQ_ERR_INVALID, "ckpt given but ckpt_every < 1");
+    sq_batch b;
+    one_scene(grid, march, prims->n, prims->n_classes, rays->n_cams, rays->height, rays->width, idx->capacity, b);
+    Plan p;
+    if ((s = make_plan(&b, tune.tile_w, p))) return s;
+    sq_batch_io io;
+    io_from(idx, prims, rays, io);
+    io.depth = depth; io.sem = sem; io.probs = probs; io.t_final = t_final; io.ckpt = ckpt;
+    io.sem_label = sem_label; io.depth_label = depth_label; io.g_depth = g_depth; io.g_sem = g_sem; io.loss = loss;
+    sq_tuning t = tuning ? *tuning : default_tuning();
+    t.chunk = march->ckpt_every;
+    return fwd_loss_checked(p, &io, weights, &t, ws, ws_bytes, stream);
+}
+
 size_t sq_voxelise_workspace(const sq_grid* grid, const sq_prims* prims) {
     return sq_render_workspace(grid, prims, nullptr, nullptr);
 }
@@ -471,6 +529,16 @@ sq_status sq_batch_render_fwd(const sq_batch* b, const sq_batch_io* io, int64_t*
     return fwd_checked(p, io, stats, tuning, ws, ws_bytes, stream);
 }
 
+sq_status sq_batch_render_fwd_loss(const sq_batch* b, const sq_batch_io* io, const sq_loss_weights* weights,
+                                   const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream) {
+    sqr::TuneDev tune;
+    sq_status s;
+    if ((s = tuning_of(tuning, tune))) return s;
+    Plan p;
+    if ((s = make_plan(b, tune.tile_w, p))) return s;
+    return fwd_loss_checked(p, io, weights, tuning, ws, ws_bytes, stream);
+}
+
 sq_status sq_batch_voxelise(const sq_batch* b, const sq_batch_io* io, float tau, void* ws, size_t ws_bytes,
                             hipStream_t stream) {
     sq_status s;
@@ -489,39 +557,41 @@ sq_status sq_batch_render_bwd(const sq_batch* b, const sq_batch_io* io, int64_t*
     return bwd_checked(p, io, stats, tuning, ws, ws_bytes, stream);
 }
 
-sq_status sq_batch_step(const sq_batch* b, const sq_batch_io* io, const sq_tuning* tuning, void* ws,
-                        size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Validates every stage of a step (index, forward, backward; with `w`, the
+// fused loss too) before the first launch.
+sq_status check_step(const sq_batch* b, const sq_batch_io* io, const sq_tuning* tuning, const sq_loss_weights* w,
+                     void* ws, size_t ws_bytes) {
     sq_status s;
-    // validate all three stages before launching the first
-    {
-        sqr::TuneDev tune;
-        if ((s = tuning_of(tuning, tune))) return s;
-        Plan p;
-        if ((s = make_plan(b, tune.tile_w, p))) return s;
-        if ((s = check_io_render(p, io))) return s;
-        if (!io->totals || !io->depth || !io->sem || !io->t_final || !io->ckpt || !io->g_means || !io->g_quats ||
-            !io->g_scales || !io->g_eps || !io->g_opacity || !io->g_logits)
-            return fail(SQ_ERR_INVALID, "a step needs totals, forward outputs, ckpt and gradient outputs");
-        const int K = chunk_of(tuning, p.m);
-        if (!(K == 4 || K == 8 || K == 16)) return fail(SQ_ERR_INVALID, "step needs a chunk in {4, 8, 16}");
-        if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
-            !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
-            return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply");
-        if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
-    }
-    if ((s = sq_batch_build_index(b, io, ws, ws_bytes, stream))) return s;
-    if ((s = sq_batch_render_fwd(b, io, nullptr, tuning, ws, ws_bytes, stream))) return s;
-    return sq_batch_render_bwd(b, io, nullptr, tuning, ws, ws_bytes, stream);
+    sqr::TuneDev tune;
+    if ((s = tuning_of(tuning, tune))) return s;
+    Plan p;
+    if ((s = make_plan(b, tune.tile_w, p))) return s;
+    if ((s = check_io_render(p, io))) return s;
+    if (!io->totals || !io->depth || !io->sem || !io->t_final || !io->ckpt || !io->g_means || !io->g_quats ||
+        !io->g_scales || !io->g_eps || !io->g_opacity || !io->g_logits)
+        return fail(SQ_ERR_INVALID, "a step needs totals, forward outputs, ckpt and gradient outputs");
+    if (w && (s = check_loss(p, io, w))) return s;
+    const int K = chunk_of(tuning, p.m);
+    if (!(K == 4 || K == 8 || K == 16)) return fail(SQ_ERR_INVALID, "step needs a chunk in {4, 8, 16}");
+    if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
+        !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
+        return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply");
+    return check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d));
 }
 
-sq_status sq_batch_step_graph_create(const sq_batch* b, const sq_batch_io* io, const sq_tuning* tuning, void* ws,
-                                     size_t ws_bytes, hipStream_t stream, sq_graph* out) {
+// Captures `launch(stream)` into an instantiated graph.
+template <typename F>
+sq_status capture_graph(hipStream_t stream, sq_graph* out, F&& launch) {
     if (!out) return fail(SQ_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!stream) return fail(SQ_ERR_INVALID, "graph capture needs a non-default stream");
     hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_status(e, "hipStreamBeginCapture");
-    const sq_status st = sq_batch_step(b, io, tuning, ws, ws_bytes, stream);
+    const sq_status st = launch(stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(stream, &graph);
     if (st != SQ_OK) {
@@ -543,6 +613,41 @@ sq_status sq_batch_step_graph_create(const sq_batch* b, const sq_batch_io* io, c
     }
     *out = reinterpret_cast<sq_graph>(g);
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+sq_status sq_batch_step(const sq_batch* b, const sq_batch_io* io, const sq_tuning* tuning, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_step(b, io, tuning, nullptr, ws, ws_bytes))) return s;
+    if ((s = sq_batch_build_index(b, io, ws, ws_bytes, stream))) return s;
+    if ((s = sq_batch_render_fwd(b, io, nullptr, tuning, ws, ws_bytes, stream))) return s;
+    return sq_batch_render_bwd(b, io, nullptr, tuning, ws, ws_bytes, stream);
+}
+
+sq_status sq_batch_train_step(const sq_batch* b, const sq_batch_io* io, const sq_loss_weights* weights,
+                              const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_step(b, io, tuning, weights, ws, ws_bytes))) return s;
+    if ((s = sq_batch_build_index(b, io, ws, ws_bytes, stream))) return s;
+    if ((s = sq_batch_render_fwd_loss(b, io, weights, tuning, ws, ws_bytes, stream))) return s;
+    return sq_batch_render_bwd(b, io, nullptr, tuning, ws, ws_bytes, stream);
+}
+
+sq_status sq_batch_step_graph_create(const sq_batch* b, const sq_batch_io* io, const sq_tuning* tuning, void* ws,
+                                     size_t ws_bytes, hipStream_t stream, sq_graph* out) {
+    return capture_graph(stream, out, [&](hipStream_t st) { return sq_batch_step(b, io, tuning, ws, ws_bytes, st); });
+}
+
+sq_status sq_batch_train_graph_create(const sq_batch* b, const sq_batch_io* io, const sq_loss_weights* weights,
+                                      const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream,
+                                      sq_graph* out) {
+    return capture_graph(stream, out, [&](hipStream_t st) {
+        return sq_batch_train_step(b, io, weights, tuning, ws, ws_bytes, st);
+    });
 }
 
 sq_status sq_graph_launch(sq_graph graph, hipStream_t stream) {

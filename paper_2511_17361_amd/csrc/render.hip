@@ -69,6 +69,13 @@ struct Ctx {
     float tau;                  // voxelisation: free-space density threshold
     float *vox_density, *vox_sem;
     int32_t* vox_labels;
+    // fused loss (Eq. eq:loss)
+    const int32_t* sem_label;
+    const float* depth_label;
+    float *gd_out, *gs_out;     // dL/dD_hat, dL/dS_hat written by the forward
+    float lam_s, lam_d;
+    const int* lcount;          // labelled pixels: semantic, depth
+    float* lpart;               // per-tile partial sums (cross-entropy, squared error)
 };
 
 // ---------------------------------------------------------------------------
@@ -124,6 +131,60 @@ __global__ __launch_bounds__(64) void k_put_desc(BatchDesc d, BatchDesc* __restr
     int* out = reinterpret_cast<int*>(dst);
     constexpr int nw = (int)(sizeof(BatchDesc) / sizeof(int));
     for (int i = threadIdx.x; i < nw; i += blockDim.x) out[i] = src[i];
+}
+
+// Labelled pixels of the fused loss: lcount[0] += semantic labels in [0, C),
+// lcount[1] += finite positive depth labels (lcount zeroed before).
+__global__ __launch_bounds__(256) void k_count_labels(int64_t n, int C, const int32_t* __restrict__ sem_label,
+                                                      const float* __restrict__ depth_label, int* lcount) {
+    __shared__ int part[2][4];
+    int ns = 0, nd = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        ns += (unsigned)sem_label[i] < (unsigned)C ? 1 : 0;
+        const float dl = depth_label[i];
+        nd += (dl > 0.0f) & (dl < INFINITY) ? 1 : 0;
+    }
+    ns = wave_sum_int(ns);
+    nd = wave_sum_int(nd);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { part[0][w] = ns; part[1][w] = nd; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0, b = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += part[0][k]; b += part[1][k]; }
+        atomicAdd(&lcount[0], a);
+        atomicAdd(&lcount[1], b);
+    }
+}
+
+// loss[0..2] = (total, L_sem, L_depth) from the per-tile partials, summed in
+// tile order (deterministic).  One block of 256 threads.
+__global__ __launch_bounds__(256) void k_loss_reduce(int tiles, const float* __restrict__ lpart,
+                                                     const int* __restrict__ lcount, float lam_s, float lam_d,
+                                                     float* loss) {
+    __shared__ double red[2][256];
+    double a = 0.0, b = 0.0;
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
+        a += (double)lpart[2 * t];
+        b += (double)lpart[2 * t + 1];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double ls = lcount[0] > 0 ? red[0][0] / lcount[0] : 0.0;
+        const double ld = lcount[1] > 0 ? red[1][0] / lcount[1] : 0.0;
+        loss[0] = (float)(lam_s * ls + lam_d * ld);
+        loss[1] = (float)ls;
+        loss[2] = (float)ld;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -303,7 +364,7 @@ __device__ __forceinline__ void for_each_marked(uint32_t* bm, int nw, int lane, 
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-template <int CP, bool CKPT, bool STATS>
+template <int CP, bool CKPT, bool STATS, bool LOSS>
 __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t* bm) {
     const SceneDev& S = P.desc->s[s];
     const RayLane rl = setup_lane(P, S, tile);
@@ -430,6 +491,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
         }
     }
 
+    float ce = 0.0f, se = 0.0f;      // this lane's loss terms (LOSS)
     if (rl.valid) {
         const int64_t ray = lane_ray(rl, S);
         P.depth[ray] = D;
@@ -440,7 +502,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
 #pragma unroll
         for (int c = 0; c < CP; ++c)
             if (c < P.C) semp[c * HW] = Sv[c];
-        if (P.probs) {
+        if (P.probs || LOSS) {
             float mx = Sv[0];
 #pragma unroll
             for (int c = 1; c < CP; ++c)
@@ -453,11 +515,47 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 sum += e[c];
             }
             const float inv = 1.0f / sum;
-            float* pp = P.probs + base;
+            if (P.probs) {
+                float* pp = P.probs + base;
 #pragma unroll
-            for (int c = 0; c < CP; ++c)
-                if (c < P.C) pp[c * HW] = e[c] * inv;
+                for (int c = 0; c < CP; ++c)
+                    if (c < P.C) pp[c * HW] = e[c] * inv;
+            }
+            if (LOSS) {
+                // Eq. eq:loss: cross-entropy of softmax(S_hat) against the class
+                // label and squared depth error, each a mean over labelled pixels;
+                // dL/dS_hat = lambda_s/N_s (softmax - onehot), dL/dD_hat = lambda_d/N_d 2 (D - D*)
+                const int lab = P.sem_label[ray];
+                const bool hs = (unsigned)lab < (unsigned)P.C;
+                float s_lab = 0.0f;
+#pragma unroll
+                for (int c = 0; c < CP; ++c)
+                    if (c == lab) s_lab = Sv[c];
+                if (hs) ce = logf(sum) + mx - s_lab;
+                const float ks = hs ? P.lam_s / (float)P.lcount[0] : 0.0f;
+                float* gp = P.gs_out + base;
+#pragma unroll
+                for (int c = 0; c < CP; ++c)
+                    if (c < P.C) gp[c * HW] = ks * (e[c] * inv - (c == lab ? 1.0f : 0.0f));
+                const float dl = P.depth_label[ray];
+                const bool hd = (dl > 0.0f) & (dl < INFINITY);
+                const float diff = hd ? D - dl : 0.0f;
+                se = diff * diff;
+                P.gd_out[ray] = hd ? (P.lam_d / (float)P.lcount[1]) * 2.0f * diff : 0.0f;
+            }
         }
+    }
+    if (LOSS) {
+        // One partial per tile, written at the tile's global index, so the final
+        // sum does not depend on which wave ran the tile.  Every lane stores lane
+        // 0's totals: a lane-divergent branch here, at the end of the body of a
+        // persistent tile loop, lets the compiler fold the branch into the
+        // loop's exit mask and split the wavefront across tiles.
+        ce = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_sum(ce))));
+        se = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wave_sum(se))));
+        const int64_t gt = (int64_t)S.tile_off + tile;
+        P.lpart[2 * gt] = ce;
+        P.lpart[2 * gt + 1] = se;
     }
     if (STATS && rl.valid) {
         atomicAdd((unsigned long long*)&P.stats[0], (unsigned long long)st_samples);
@@ -469,7 +567,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
 
 // Dynamic LDS: waves_per_block x bitmap_words words (zero bitmap_words: no
 // union bitmap; mixed-voxel samples then walk one voxel group at a time).
-template <int CP, bool CKPT, bool STATS, bool PERSIST>
+template <int CP, bool CKPT, bool STATS, bool PERSIST, bool LOSS = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP, CKPT, STATS, PERSIST), 8))) void k_render_fwd(Ctx P) {
     extern __shared__ uint32_t bm_all[];
     uint32_t* bm = nullptr;
@@ -481,7 +579,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP,
     }
     for_each_tile<PERSIST>(P, [&](int t, const Ctx& Q) {
         const int s = find_scene(Q.desc, t);
-        fwd_tile<CP, CKPT, STATS>(Q, s, t - Q.desc->s[s].tile_off, bm);
+        fwd_tile<CP, CKPT, STATS, LOSS>(Q, s, t - Q.desc->s[s].tile_off, bm);
     });
 }
 
@@ -1075,7 +1173,7 @@ void finish_desc(BatchDesc& d, int tile_w) {
 }
 
 struct WsSizes {
-    size_t desc, queue, boxes, partials, rec, lgp, acc;
+    size_t desc, queue, boxes, partials, rec, lgp, acc, lcount, lpart;
 };
 static WsSizes ws_sizes(const GridDev& g, const BatchDesc& d) {
     const int CP = padded_classes(d.C);
@@ -1087,12 +1185,14 @@ static WsSizes ws_sizes(const GridDev& g, const BatchDesc& d) {
     z.rec = align_up((size_t)d.total_prims * REC * sizeof(float));
     z.lgp = align_up((size_t)d.total_prims * CP * sizeof(float));
     z.acc = align_up((size_t)d.total_prims * acc_row(CP) * sizeof(float));
+    z.lcount = align_up(2 * sizeof(int));
+    z.lpart = align_up((size_t)d.total_tiles * 2 * sizeof(float));
     return z;
 }
 
 size_t batch_workspace_bytes(const GridDev& g, const BatchDesc& d) {
     const WsSizes z = ws_sizes(g, d);
-    return z.desc + z.queue + z.boxes + z.partials + z.rec + z.lgp + z.acc;
+    return z.desc + z.queue + z.boxes + z.partials + z.rec + z.lgp + z.acc + z.lcount + z.lpart;
 }
 
 size_t index_workspace_bytes(const GridDev& g, const BatchDesc& d) {
@@ -1110,7 +1210,9 @@ WsLayout carve_ws(void* ws, const GridDev& g, const BatchDesc& d) {
     l.partials = (int64_t*)p; p += z.partials;
     l.rec = (float*)p; p += z.rec;
     l.lgp = (float*)p; p += z.lgp;
-    l.acc = (float*)p;
+    l.acc = (float*)p; p += z.acc;
+    l.lcount = (int*)p; p += z.lcount;
+    l.lpart = (float*)p;
     return l;
 }
 
@@ -1173,6 +1275,10 @@ static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, co
     P.bitmap_words = bitmap_words(d.max_n);
     P.tau = 0.0f;
     P.vox_density = io.vox_density; P.vox_sem = io.vox_sem; P.vox_labels = io.vox_labels;
+    P.sem_label = io.sem_label; P.depth_label = io.depth_label;
+    P.gd_out = const_cast<float*>(io.g_depth); P.gs_out = const_cast<float*>(io.g_sem);
+    P.lam_s = P.lam_d = 0.0f;
+    P.lcount = l.lcount; P.lpart = l.lpart;
     return P;
 }
 
@@ -1181,40 +1287,62 @@ static bool bitmap_fits(int max_n, int wpb) {
     return (size_t)wpb * bitmap_words(max_n) * sizeof(uint32_t) <= 64 * 1024;
 }
 
+template <int CP, bool LOSS>
+static void fwd_launch(const Ctx& P, const TuneDev& t, size_t shm, hipStream_t st) {
+    const int wpb = t.waves_per_block;
+    const bool ck = P.ckpt != nullptr;
+    if (t.persistent) {
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, P.queue, N_XCD * QUEUE_STRIDE, 0);
+        if (ck) launch_tiles(k_render_fwd<CP, true, false, true, LOSS>, true, P, wpb, shm, st);
+        else launch_tiles(k_render_fwd<CP, false, false, true, LOSS>, true, P, wpb, shm, st);
+    } else {
+        if (ck) launch_tiles(k_render_fwd<CP, true, false, false, LOSS>, false, P, wpb, shm, st);
+        else launch_tiles(k_render_fwd<CP, false, false, false, LOSS>, false, P, wpb, shm, st);
+    }
+}
+
 template <int CP>
 static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P0,
-                    const TuneDev& t, hipStream_t st) {
+                    const TuneDev& t, hipStream_t st, const LossArgs* loss) {
     prep_records<CP>(d, g, io, l, st);
     const int wpb = t.waves_per_block;
     Ctx P = P0;
     if (!bitmap_fits(d.max_n, wpb)) P.bitmap_words = 0;
     const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);
     const bool ck = P.ckpt != nullptr, stt = P.stats != nullptr;
+    if (loss) {
+        // labelled-pixel counts first: the forward's epilogue divides by them
+        P.lam_s = loss->lambda_sem;
+        P.lam_d = loss->lambda_depth;
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, l.lcount, 2, 0);
+        if (d.total_rays > 0) {
+            const int64_t blocks = std::min<int64_t>((d.total_rays + 255) / 256, 2048);
+            hipLaunchKernelGGL(k_count_labels, dim3((unsigned)blocks), dim3(256), 0, st, (int64_t)d.total_rays, d.C,
+                               io.sem_label, io.depth_label, l.lcount);
+        }
+        fwd_launch<CP, true>(P, t, shm, st);
+        hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, d.total_tiles, (const float*)l.lpart,
+                           (const int*)l.lcount, loss->lambda_sem, loss->lambda_depth, io.loss);
+        return;
+    }
     if (stt) {
         if (ck) launch_tiles(k_render_fwd<CP, true, true, false>, false, P, wpb, shm, st);
         else launch_tiles(k_render_fwd<CP, false, true, false>, false, P, wpb, shm, st);
         return;
     }
-    if (t.persistent) {
-        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, P.queue, N_XCD * QUEUE_STRIDE, 0);
-        if (ck) launch_tiles(k_render_fwd<CP, true, false, true>, true, P, wpb, shm, st);
-        else launch_tiles(k_render_fwd<CP, false, false, true>, true, P, wpb, shm, st);
-    } else {
-        if (ck) launch_tiles(k_render_fwd<CP, true, false, false>, false, P, wpb, shm, st);
-        else launch_tiles(k_render_fwd<CP, false, false, false>, false, P, wpb, shm, st);
-    }
+    fwd_launch<CP, false>(P, t, shm, st);
 }
 
 hipError_t launch_batch_fwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
-                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st) {
+                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st, const LossArgs* loss) {
     const WsLayout l = carve_ws(ws, g, d);
     put_desc(d, l.desc, st);
     const Ctx P = make_ctx(g, d, mr, io, l, stats);
     switch (padded_classes(d.C)) {
-        case 4: fwd_run<4>(g, d, io, l, P, tune, st); break;
-        case 8: fwd_run<8>(g, d, io, l, P, tune, st); break;
-        case 17: fwd_run<17>(g, d, io, l, P, tune, st); break;
-        default: fwd_run<32>(g, d, io, l, P, tune, st); break;
+        case 4: fwd_run<4>(g, d, io, l, P, tune, st, loss); break;
+        case 8: fwd_run<8>(g, d, io, l, P, tune, st, loss); break;
+        case 17: fwd_run<17>(g, d, io, l, P, tune, st, loss); break;
+        default: fwd_run<32>(g, d, io, l, P, tune, st, loss); break;
     }
     return hipGetLastError();
 }

@@ -68,6 +68,14 @@ struct BatchIO {
     float *g_means, *g_quats, *g_scales, *g_eps, *g_opacity, *g_logits;
     float *vox_density, *vox_sem;
     int32_t* vox_labels;
+    const int32_t* sem_label;
+    const float* depth_label;
+    float* loss;
+};
+
+// Weights of the fused loss (Eq. eq:loss); nullptr = no loss epilogue.
+struct LossArgs {
+    float lambda_sem, lambda_depth;
 };
 
 // class count padded to the compiled widths
@@ -82,7 +90,8 @@ size_t index_workspace_bytes(const GridDev& g, const BatchDesc& d);
 
 hipError_t launch_batch_index(const GridDev& g, const BatchDesc& d, const BatchIO& io, void* ws, hipStream_t st);
 hipError_t launch_batch_fwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
-                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
+                            int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st,
+                            const LossArgs* loss = nullptr);
 hipError_t launch_batch_bwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
                             int64_t* stats, const TuneDev& tune, void* ws, hipStream_t st);
 

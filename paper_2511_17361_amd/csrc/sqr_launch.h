@@ -13,6 +13,8 @@ namespace sqr {
 //   rec       [total_prims x REC] prepared primitive records
 //   lgp       [total_prims x CP] logits padded to the compiled class width
 //   acc       [total_prims x VP] backward gradient accumulators
+//   lcount    2 ints: labelled pixels (semantic, depth) of the fused loss
+//   lpart     [total_tiles x 2] per-tile loss partial sums
 struct WsLayout {
     BatchDesc* desc;
     int* queue;
@@ -21,6 +23,8 @@ struct WsLayout {
     float* rec;
     float* lgp;
     float* acc;
+    int* lcount;
+    float* lpart;
 };
 
 int acc_row(int CP);

@@ -229,6 +229,19 @@ def upstream_grads(rng, rays: Rays, n_classes: int):
     return g_d, g_s
 
 
+def pseudo_labels(rng, rays: Rays, n_classes: int, t_near: float, t_far: float, unlabelled: float = 0.15):
+    """Stand-ins for the 2D pseudo-labels of the training loss (semantic
+    class per pixel, metric depth per pixel), layouts [cams,H,W]: classes
+    uniform in [0, C) with a fraction `unlabelled` set to -1, depths uniform in
+    [t_near, t_far] with a fraction `unlabelled` set to 0 (no depth)."""
+    c, h, w = rays.shape
+    sem = rng.integers(0, n_classes, (c, h, w)).astype(np.int32)
+    sem[rng.random((c, h, w)) < unlabelled] = -1
+    depth = _f32(rng.uniform(t_near, t_far, (c, h, w)))
+    depth[rng.random((c, h, w)) < unlabelled] = 0.0
+    return sem, depth
+
+
 def sub_rays(rays: Rays, cams=None, rows=None, cols=None) -> Rays:
     """A rectangular window of the rig (same layout, smaller H/W)."""
     o, d = rays.origins, rays.dirs
