@@ -264,22 +264,29 @@ def _eval_pairs(P: _Prep, x, k):
 
 
 def _march(grid, prims, rays_o, rays_d, march, index, brute, P, want_pairs):
-    """Front-to-back march of a ray batch.  Returns per-ray renders and, if
-    asked, the per-sample/pair records the adjoint replays."""
+    """Front-to-back march of a ray batch.  Returns per-ray depth, semantics
+    and final transmittance, the per-sample/pair records the adjoint replays
+    (if asked) and, with early termination, each ray's smallest relative
+    distance |T_j / kappa - 1| over the transmittances it compared (inf without)."""
     B = rays_o.shape[0]
     C = prims.logits.shape[1]
     counts, offsets, ids = index if index is not None else (None, None, None)
     box_lo, box_hi = centre_boxes(prims.means, grid) if brute else (None, None)
     t32 = sample_depths(march.n_samples, march.t_near, march.t_far)
+    kappa = float(getattr(march, "kappa", 0.0))
     T = np.ones(B)
     depth = np.zeros(B)
     sem = np.zeros((B, C))
+    margin = np.full(B, np.inf)
     records = []
     for j, tj in enumerate(t32):
         x32 = (rays_o + (tj * rays_d).astype(F32)).astype(F32)       # pinned FP32 point
         inside, v = voxel_of_points(x32, grid)
-        # rays with T == 0 contribute exactly zero from here on (T_{j+1} = 0 * ...)
-        active = inside & (T > 0)
+        # rays with T == 0 contribute exactly zero from here on (T_{j+1} = 0 * ...);
+        # early termination (Sec. "Ray Termination"): a ray stops once T < kappa
+        if kappa > 0:
+            margin = np.minimum(margin, np.abs(T / kappa - 1.0))
+        active = inside & (T > 0) & (T >= kappa)
         r_rep, k = _pairs_for_sample(v, active, counts, offsets, ids, box_lo, box_hi, grid, brute)
         a = np.zeros(B)
         s = np.zeros((B, C))
@@ -296,7 +303,9 @@ def _march(grid, prims, rays_o, rays_d, march, index, brute, P, want_pairs):
             records.append(dict(t=np.float64(tj), a=a, alpha=alpha, T=T.copy(), w=w, s=s,
                                 r=r_rep, k=k, x=(x32[r_rep].astype(np.float64) if r_rep.size else None)))
         T = T * (1.0 - alpha)
-    return depth, sem, T, records
+    if kappa > 0:
+        margin = np.minimum(margin, np.abs(T / kappa - 1.0))
+    return depth, sem, T, records, margin
 
 
 def _softmax(z):
@@ -328,17 +337,18 @@ def render(grid, prims, rays, march, index=None, brute=False, ray_ids=None, batc
     depth = np.zeros(n)
     sem = np.zeros((n, C))
     tfin = np.zeros(n)
+    margin = np.zeros(n)
     for s, e in _ray_batches(n, batch):
-        dd, ss, tt, _ = _march(grid, prims, o[s:e], d[s:e], march, index, brute, P, False)
-        depth[s:e], sem[s:e], tfin[s:e] = dd, ss, tt
+        dd, ss, tt, _, mm = _march(grid, prims, o[s:e], d[s:e], march, index, brute, P, False)
+        depth[s:e], sem[s:e], tfin[s:e], margin[s:e] = dd, ss, tt, mm
     probs = _softmax(sem)
     if ray_ids is not None:
-        return dict(depth=depth, sem=sem, probs=probs, t_final=tfin)
+        return dict(depth=depth, sem=sem, probs=probs, t_final=tfin, kappa_margin=margin)
     cams, H, W = rays.shape
     return dict(depth=depth.reshape(cams, H, W),
                 sem=sem.reshape(cams, H, W, C).transpose(0, 3, 1, 2).copy(),
                 probs=probs.reshape(cams, H, W, C).transpose(0, 3, 1, 2).copy(),
-                t_final=tfin.reshape(cams, H, W))
+                t_final=tfin.reshape(cams, H, W), kappa_margin=margin.reshape(cams, H, W))
 
 
 # ---------------------------------------------------------------------------
@@ -437,7 +447,7 @@ def render_grad(grid, prims, rays, march, g_depth, g_sem, index=None, brute=Fals
                eps=np.zeros((N, 2)), opacity=np.zeros(N), logits=np.zeros((N, C)))
     n = o.shape[0]
     for s0, e0 in _ray_batches(n, batch):
-        _, _, _, recs = _march(grid, prims, o[s0:e0], d[s0:e0], march, index, brute, P, True)
+        _, _, _, recs, _ = _march(grid, prims, o[s0:e0], d[s0:e0], march, index, brute, P, True)
         gd = gD[s0:e0]
         gs = gS[s0:e0]
         Q = np.zeros(e0 - s0)

@@ -81,6 +81,7 @@ class March:
     t_near: float
     t_far: float
     ckpt_every: int = 0
+    kappa: float = 0.0     # early ray termination threshold (0 = none)
 
 
 @dataclass

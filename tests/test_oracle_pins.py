@@ -371,7 +371,7 @@ def _march_records(sc):
 @pytest.mark.parametrize("seed", [13, 14])
 def test_compositing_invariants(seed):
     sc = random_scene(seed, n=15, width=6, height=5, n_samples=24)
-    depth, sem, tfin, recs = _march_records(sc)
+    depth, sem, tfin, recs, _ = _march_records(sc)
     W = np.stack([r["w"] for r in recs], 1)
     T = np.stack([r["T"] for r in recs], 1)
     A = np.stack([r["alpha"] for r in recs], 1)
@@ -458,7 +458,7 @@ def test_adjoint_matches_central_differences_unclamped():
 def test_adjoint_matches_central_differences_with_clamping():
     sc = random_scene(21, n=8, n_classes=2, width=4, height=3, n_samples=14, opacity_hi=1.0,
                       scale_lo=0.7, scale_hi=1.5)
-    depth, sem, tfin, recs = _march_records(sc)
+    depth, sem, tfin, recs, _ = _march_records(sc)
     assert any(np.any(r["a"] >= 1) for r in recs)       # the clamp is exercised
     checked, worst = _fd_check(sc, seed=1)
     assert checked >= 8 * 15 * 0.7
@@ -470,7 +470,7 @@ def test_logit_gradient_closed_form():
     rng = np.random.default_rng(2)
     g_d, g_s = synth.upstream_grads(rng, sc.rays, 3)
     grads = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
-    depth, sem, tfin, recs = _march_records(sc)
+    depth, sem, tfin, recs, _ = _march_records(sc)
     gS = g_s.transpose(0, 2, 3, 1).reshape(-1, 3).astype(np.float64)
     want = np.zeros((sc.prims.n, 3))
     P = oracle.sqr_oracle._Prep(sc.prims)
