@@ -225,6 +225,30 @@ def main():
     batch.release_graph()
     train_loss = [float(x) for x in batch.buf["loss"].cpu().tolist()]
 
+    # early ray termination (Supplement "Ray Termination"): the step and the forward at kappa = 1e-4, 1e-2
+    kappa_ms = {}
+    for kappa in (1e-4, 1e-2):
+        batch.set_kappa(kappa)
+        batch.capture(tune, stream=stream)
+        for _ in range(args.warmup):
+            batch.replay(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.replay(stream)
+        torch.cuda.synchronize()
+        step_k = (time.perf_counter() - t0) * 1e3 / args.steps
+        batch.release_graph()
+        ke = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        with torch.cuda.stream(stream):
+            ke[0].record(stream)
+            for _ in range(args.steps):
+                batch.render_fwd(tune, stream=stream)
+            ke[1].record(stream)
+        torch.cuda.synchronize()
+        kappa_ms[f"{kappa:g}"] = dict(step_ms=step_k, fwd_ms=ke[0].elapsed_time(ke[1]) / args.steps)
+    batch.set_kappa(0.0)
+
     # voxelisation of each scene's grid (Eq. eq:voxelisation, tau = 0.05) from the same index
     vox = [api.voxelise(grid, idx, p, tau=0.05) for p, r, idx, out in plain]
     torch.cuda.synchronize()
@@ -266,6 +290,7 @@ def main():
         "rays_per_s_fwd_bwd": R / (ms_step / 1e3),
         "index_ms": t_idx, "fwd_ms": t_fwd, "bwd_ms": t_bwd, "plain_fwd_ms": t_plain,
         "index_entries": sum(E),
+        "kappa_ms": kappa_ms,
         "train_step_ms": ms_train,
         "train_ray_samples_per_s": R * Ls / (ms_train / 1e3),
         "train_loss": train_loss,

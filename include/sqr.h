@@ -105,12 +105,19 @@ typedef struct {
  *   i = floor(fl(fl(x_j - lo) * fl(1/voxel))).
  * ckpt_every (K) is the transmittance-checkpoint spacing used by the
  * differentiable forward and the backward; 0 = no checkpoints.
- * Requires L >= 1 and 0 <= t_near < t_far (t_near <= t_far if L == 1). */
+ * kappa is the early ray termination threshold (Supplement "Ray
+ * Termination"): sample j is composited only while its transmittance
+ * T_j >= kappa, so a ray stops once T falls below kappa; the backward
+ * differentiates the truncated render (the stopping point itself carries no
+ * gradient).  0 = no termination (the paper's default); requires
+ * 0 <= kappa <= 1.  Requires L >= 1 and 0 <= t_near < t_far (t_near <= t_far
+ * if L == 1). */
 typedef struct {
     int32_t n_samples;
     float   t_near;
     float   t_far;
     int32_t ckpt_every;
+    float   kappa;
 } sq_march;
 
 /* Gradient outputs (overwritten, not accumulated), shaped like sq_prims. */

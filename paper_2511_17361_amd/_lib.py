@@ -50,7 +50,7 @@ class SqRays(ct.Structure):
 
 class SqMarch(ct.Structure):
     _fields_ = [("n_samples", ct.c_int32), ("t_near", ct.c_float), ("t_far", ct.c_float),
-                ("ckpt_every", ct.c_int32)]
+                ("ckpt_every", ct.c_int32), ("kappa", ct.c_float)]
 
 
 class SqGrads(ct.Structure):

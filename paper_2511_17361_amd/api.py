@@ -8,6 +8,7 @@ workspace with torch, and calls one C entry point.
 from __future__ import annotations
 
 import ctypes as ct
+import dataclasses
 from dataclasses import dataclass
 from typing import Optional
 
@@ -62,6 +63,7 @@ class March:
     t_near: float
     t_far: float
     ckpt_every: int = 0
+    kappa: float = 0.0      # early ray termination threshold (0 = none)
 
     def c(self, ckpt_every: Optional[int] = None) -> L.SqMarch:
         m = L.SqMarch()
@@ -69,12 +71,14 @@ class March:
         m.t_near = float(self.t_near)
         m.t_far = float(self.t_far)
         m.ckpt_every = int(self.ckpt_every if ckpt_every is None else ckpt_every)
+        m.kappa = float(self.kappa)
         return m
 
     @staticmethod
     def of(obj) -> "March":
         return obj if isinstance(obj, March) else March(int(obj.n_samples), float(obj.t_near), float(obj.t_far),
-                                                        int(getattr(obj, "ckpt_every", 0)))
+                                                        int(getattr(obj, "ckpt_every", 0)),
+                                                        float(getattr(obj, "kappa", 0.0)))
 
 
 @dataclass
@@ -483,6 +487,11 @@ class Batch:
         return dict(density=self.buf["vox_density"][i * V:(i + 1) * V].view(X, Y, Z),
                     sem=self.buf["vox_sem"][i * C * V:(i + 1) * C * V].view(C, X, Y, Z),
                     labels=self.buf["vox_labels"][i * V:(i + 1) * V].view(X, Y, Z))
+
+    def set_kappa(self, kappa: float):
+        """Early ray termination threshold of later calls (captured graphs keep theirs)."""
+        self.march = dataclasses.replace(self.march, kappa=float(kappa))
+        self.c_batch.march.kappa = float(kappa)
 
     def set_labels(self, i, sem_label, depth_label):
         """Scene i's pseudo-labels for the fused loss: sem_label int32 and

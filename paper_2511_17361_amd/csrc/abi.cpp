@@ -68,6 +68,7 @@ sq_status check_march(const sq_march* m) {
     if (m->n_samples > 1 ? !(m->t_near < m->t_far) : !(m->t_near <= m->t_far))
         return fail(SQ_ERR_INVALID, "need t_near < t_far (got %g, %g)", m->t_near, m->t_far);
     if (m->ckpt_every < 0) return fail(SQ_ERR_INVALID, "ckpt_every < 0");
+    if (!(m->kappa >= 0.0f && m->kappa <= 1.0f)) return fail(SQ_ERR_INVALID, "kappa must lie in [0, 1]");
     return SQ_OK;
 }
 
@@ -79,6 +80,7 @@ sqr::MarchDev to_dev(const sq_march* m, int K) {
     const float span = m->t_far - m->t_near;
     d.delta = m->n_samples > 1 ? span / (float)(m->n_samples - 1) : 0.0f;
     d.K = K;
+    d.kappa = m->kappa;
     return d;
 }
 
@@ -343,7 +345,7 @@ struct GraphImpl {
     hipGraphExec_t exec;
 };
 
-const sq_march kIndexMarch = {1, 0.0f, 1.0f, 0};
+const sq_march kIndexMarch = {1, 0.0f, 1.0f, 0, 0.0f};
 
 }  // namespace
 
@@ -351,7 +353,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 202; }
+int32_t sq_version(void) { return 203; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 

@@ -481,7 +481,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
 #pragma unroll
             for (int c = 0; c < CP; ++c) Sv[c] = fmaf(w, sv[c], Sv[c]);
             T = T * (1.0f - alpha);
-            alive = alive && (T > 0.0f);
+            alive = alive && (T > 0.0f) && (T >= P.mr.kappa);
         }
         if (wave_ballot(alive) == 0) {
             // every later sample of this tile is exactly zero
@@ -706,6 +706,7 @@ __device__ __forceinline__ void bwd_sm_tile(const Ctx& P, int s, int tile, float
     const int nck = (L + K - 1) / K;
     const float* ckpt = P.ckpt + (int64_t)nck * S.ray_off;
     float* acc = P.acc + (size_t)S.prim_off * VP;
+    const float kappa = P.mr.kappa;
 
     const float gD = (rl.valid && P.g_depth) ? P.g_depth[lane_ray(rl, S)] : 0.0f;
     float gS[CP];
@@ -717,7 +718,7 @@ __device__ __forceinline__ void bwd_sm_tile(const Ctx& P, int s, int tile, float
     int64_t st[6] = {0, 0, 0, 0, 0, 0};   // samples, listed, evaluated pairs of pass 1 and of pass 2
     for (int ci = nck - 1; ci >= 0; --ci) {
         const float Tc = rl.valid ? ckpt[(int64_t)ci * R + lane_lray(rl, S)] : 0.0f;
-        if (wave_ballot(Tc > 0.0f) == 0) continue;
+        if (wave_ballot((Tc > 0.0f) && (Tc >= kappa)) == 0) continue;
         const int j0 = ci * K;
         const int jn = min(K, L - j0);
 
@@ -727,7 +728,10 @@ __device__ __forceinline__ void bwd_sm_tile(const Ctx& P, int s, int tile, float
             const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
                                                rl.dx, rl.dy, rl.dz);
             int n = 0, f = 0;
-            bool act = (T > 0.0f) && (sp.v >= 0);
+            // a sample the forward composited: T_j > 0 and T_j >= kappa (the same
+            // float32 T_j, bit for bit, as the forward's)
+            const bool pres = (T > 0.0f) && (T >= kappa);
+            bool act = pres && (sp.v >= 0);
             if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
             if (STATS && act) { st[0] += 1; st[1] += n; }
             float a = 0.0f, G = 0.0f;
@@ -759,7 +763,7 @@ __device__ __forceinline__ void bwd_sm_tile(const Ctx& P, int s, int tile, float
                 pend = pend && !mine;
             }
             sm_a[jj * 64 + lane] = a;
-            sm_T[jj * 64 + lane] = T;
+            sm_T[jj * 64 + lane] = pres ? T : 0.0f;    // absent samples: no weight, no adjoint
             sm_G[jj * 64 + lane] = fmaf(gD, sp.t, G);
             T = T * (1.0f - fminf(a, 1.0f));
         }
@@ -900,6 +904,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
     const int nck = (L + KC - 1) / KC;
     const float* ckpt = P.ckpt + (int64_t)nck * S.ray_off;
     float* acc = P.acc + (size_t)S.prim_off * VP;
+    const float kappa = P.mr.kappa;
 
     const float gD = (rl.valid && P.g_depth) ? P.g_depth[lane_ray(rl, S)] : 0.0f;
     float gS[CP];
@@ -911,7 +916,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
     float Q = 0.0f;
     for (int ci = nck - 1; ci >= 0; --ci) {
         const float Tc = rl.valid ? ckpt[(int64_t)ci * R + lane_lray(rl, S)] : 0.0f;
-        if (wave_ballot(Tc > 0.0f) == 0) continue;
+        if (wave_ballot((Tc > 0.0f) && (Tc >= kappa)) == 0) continue;
         const int j0 = ci * KC;
 
         // ---- chunk geometry + bitmap of the listed ids ----------------------
@@ -929,7 +934,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                                                    rl.dx, rl.dy, rl.dz);
                 sx[jj] = sp.x; sy[jj] = sp.y; sz[jj] = sp.z;
                 int n = 0, f = 0;
-                bool act = (Tc > 0.0f) && (sp.v >= 0);
+                bool act = (Tc > 0.0f) && (Tc >= kappa) && (sp.v >= 0);
                 if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
                 if (act) pv[jj] = pack_voxel(sp.ix, sp.iy, sp.iz);
                 bool pend = act;
@@ -985,18 +990,22 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         // ---- compositing and its adjoint (per lane) -------------------------
         float Tj[KC];
         {
+            // the forward composited sample j only while T_j > 0 and T_j >= kappa;
+            // absent samples get T_j = 0 here (no weight, no adjoint) and leave T as is
             float T = Tc;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
-                Tj[jj] = T;
-                T = T * (1.0f - fminf(a[jj], 1.0f));
+                const bool pres = (T > 0.0f) && (T >= kappa);
+                Tj[jj] = pres ? T : 0.0f;
+                if (pres) T = T * (1.0f - fminf(a[jj], 1.0f));
             }
         }
 #pragma unroll
         for (int jj = KC - 1; jj >= 0; --jj) {
             if (j0 + jj < L) {
                 const float t = P.mr.t_near + (float)(j0 + jj) * P.mr.delta;
-                const float al = fminf(a[jj], 1.0f);
+                // absent samples (T_j = 0 here) pass Q through unchanged
+                const float al = Tj[jj] > 0.0f ? fminf(a[jj], 1.0f) : 0.0f;
                 const float Gf = fmaf(gD, t, G[jj]);
                 const float dal = Tj[jj] * (Gf - Q);
                 Q = fmaf(al, Gf, (1.0f - al) * Q);

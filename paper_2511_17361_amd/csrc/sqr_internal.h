@@ -48,6 +48,7 @@ struct MarchDev {
     int L;
     float t_near, delta;
     int K;      // checkpoint spacing (0 = none)
+    float kappa;  // early ray termination: a ray stops once T < kappa (0 = none)
 };
 
 struct TuneDev {

@@ -244,3 +244,14 @@ def test_batch_calls_reject_bad_tuning_chunk_and_workspace():
     bad = _batch()
     bad.n_scenes = 40
     assert lib.sq_batch_workspace(ct.byref(bad)) == 0
+
+
+@pytest.mark.parametrize("kappa", [-0.1, 1.5, float("nan"), float("inf")])
+def test_march_kappa_outside_unit_interval_is_rejected(kappa):
+    lib = L.load()
+    m = _march(K=4)
+    m.kappa = kappa
+    t = L.SqTuning(8, 4, 0, 0, 0)
+    rc = lib.sq_render_fwd(ct.byref(_grid()), ct.byref(_index()), ct.byref(_prims()), ct.byref(_rays()), ct.byref(m),
+                           FAKE, FAKE, None, FAKE, None, None, ct.byref(t), 0x100000, 1 << 30, None)
+    assert rc == L.SQ_ERR_INVALID and "kappa" in lib.sq_last_error().decode()
