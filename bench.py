@@ -121,6 +121,46 @@ def cpu_baseline(sc, n_rays, seed=0):
                        f"one process ({dt:.1f} s); index build excluded")
 
 
+def sq_major_ab(dev, steps, K=4):
+    """A/B of the two backward strategies on the 6,400-superquadric workload
+    (6 cameras x 352x200 rays, L = 100): the default wavefront-reduced
+    atomics against the superquadric-major grouping of interactions."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2511_17361_amd import api
+    sc = synth.config(1)
+    grid, march = api.Grid.of(sc.grid), api.March(sc.march.n_samples, sc.march.t_near, sc.march.t_far, K)
+    prims, rays = api.Prims.from_numpy(sc.prims, dev), api.Rays.from_numpy(sc.rays, dev)
+    idx = api.build_index(grid, prims)
+    out = api.render_fwd(grid, idx, prims, rays, march, ckpt_every=K)
+    gd, gs = synth.upstream_grads(np.random.default_rng(4), sc.rays, sc.prims.n_classes)
+    gd, gs = torch.from_numpy(gd).to(dev), torch.from_numpy(gs).to(dev)
+    probe = api.render_bwd_sq_major(grid, idx, prims, rays, march, out["ckpt"], K, gd, gs, 0)
+    torch.cuda.synchronize()
+    E = int(probe["interactions"].item())
+    iws = None
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(steps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    lib_ws = {}
+    t_atomic = timed(lambda: api.render_bwd(grid, idx, prims, rays, march, out["ckpt"], K, gd, gs))
+    t_sqm = timed(lambda: lib_ws.__setitem__("g", api.render_bwd_sq_major(grid, idx, prims, rays, march,
+                                                                          out["ckpt"], K, gd, gs, E)))
+    return dict(workload="6,400 superquadrics, 6 cameras x 352x200 rays, L=100, K=4", interactions=E,
+                atomics_ms=t_atomic, sq_major_ms=t_sqm)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -325,6 +365,8 @@ def main():
                               "traffic": recorded_traffic(kname), "flop_per_launch": f_bwd, "kernel_ms": t_bwd,
                               "peak_nonpacked": VALU_NONPACKED_TFLOPS,
                               "frac_nonpacked": ach / VALU_NONPACKED_TFLOPS}
+
+    result["sq_major_ab"] = sq_major_ab(dev, args.steps)
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4

@@ -225,6 +225,29 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
                         const sq_grads* grads, int64_t* stats, const sq_tuning* tuning,
                         void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Bytes of the interaction workspace sq_render_bwd_sq_major needs for
+ * `capacity` interactions (host-only; 0 on bad input). */
+size_t sq_sq_major_workspace(const sq_grid* grid, const sq_prims* prims, const sq_rays* rays,
+                             const sq_march* march, int64_t capacity);
+
+/* sq_render_bwd computed superquadric-major, as the paper's Processes 1-3
+ * (Sec. 3.3 "Backward Pass"): (1) per ray, replay the checkpointed chunks and
+ * store dL/da_j and w_j per sample; (2) build the set of (primitive, sample)
+ * interactions from the index and group it by primitive id (count, scan,
+ * scatter: a counting sort); (3) reduce each primitive's group in one block,
+ * without global atomics.  Same results as sq_render_bwd (to rounding).  An
+ * A/B alternative to the default backward: it needs the caller's interaction
+ * workspace (iws, sq_sq_major_workspace bytes) holding up to `capacity`
+ * interactions; *interactions (one device int64) receives their number E; if
+ * E > capacity the gradients are incomplete and the call must be repeated
+ * with more (check after a sync, as for sq_build_index).  Requires
+ * rays x samples < 2^32. */
+sq_status sq_render_bwd_sq_major(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
+                                 const sq_rays* rays, const sq_march* march, const float* ckpt,
+                                 const float* g_depth, const float* g_sem, const sq_grads* grads,
+                                 int64_t capacity, int64_t* interactions, void* iws, size_t iws_bytes,
+                                 const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Weights of the training loss of Eq. eq:loss (Supplement "Loss
  * Formulation"): L = lambda_sem * L_sem + lambda_depth * L_depth; the paper
  * uses lambda_sem = 2, lambda_depth = 0.05. */

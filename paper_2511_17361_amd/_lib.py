@@ -26,6 +26,7 @@ EXPORTED = [
     "sq_batch_step_graph_create", "sq_graph_launch", "sq_graph_destroy", "sq_batch_autotune",
     "sq_voxelise_workspace", "sq_voxelise", "sq_batch_voxelise",
     "sq_render_fwd_loss", "sq_batch_render_fwd_loss", "sq_batch_train_step", "sq_batch_train_graph_create",
+    "sq_sq_major_workspace", "sq_render_bwd_sq_major",
 ]
 
 
@@ -163,6 +164,13 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.sq_batch_train_graph_create.restype = ct.c_int32
     lib.sq_batch_train_graph_create.argtypes = [P(SqBatch), P(SqBatchIO), P(SqLossWeights), P(SqTuning),
                                                 ct.c_void_p, ct.c_size_t, ct.c_void_p, P(ct.c_void_p)]
+    lib.sq_sq_major_workspace.restype = ct.c_size_t
+    lib.sq_sq_major_workspace.argtypes = [P(SqGrid), P(SqPrims), P(SqRays), P(SqMarch), ct.c_int64]
+    lib.sq_render_bwd_sq_major.restype = ct.c_int32
+    lib.sq_render_bwd_sq_major.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch), ct.c_void_p,
+                                           ct.c_void_p, ct.c_void_p, P(SqGrads), ct.c_int64, ct.c_void_p,
+                                           ct.c_void_p, ct.c_size_t, P(SqTuning), ct.c_void_p, ct.c_size_t,
+                                           ct.c_void_p]
     _lib = lib
     return lib
 

@@ -281,6 +281,39 @@ def render_bwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt: torch.
     return out
 
 
+def render_bwd_sq_major(grid, index: Index, prims: Prims, rays: Rays, march, ckpt: torch.Tensor, ckpt_every: int,
+                        g_depth: Optional[torch.Tensor], g_sem: Optional[torch.Tensor], capacity: int,
+                        tuning: Optional[Tuning] = None, stream=None, iws: Optional[torch.Tensor] = None,
+                        out: Optional[dict] = None) -> dict:
+    """sq_render_bwd_sq_major: the superquadric-major backward (interactions
+    grouped by primitive).  Returns the gradients and `interactions` (device
+    int64: the number of interactions; results are valid when it is <=
+    capacity)."""
+    lib = L.load()
+    grid, march = Grid.of(grid), March.of(march)
+    dev = prims.means.device
+    if out is None:
+        out = {name: torch.empty_like(getattr(prims, name))
+               for name in ("means", "quats", "scales", "eps", "opacity", "logits")}
+    out["interactions"] = torch.zeros(1, dtype=torch.int64, device=dev)
+    gr = L.SqGrads(*(_ptr(out[name]) for name in ("means", "quats", "scales", "eps", "opacity", "logits")))
+    g, p, r, m = grid.c(), prims.c(), rays.c(), march.c(ckpt_every)
+    ix = index.c()
+    t = (tuning or Tuning()).c()
+    need = lib.sq_render_workspace(ct.byref(g), ct.byref(p), ct.byref(r), ct.byref(m))
+    wbuf = _workspace(need, dev)
+    ineed = lib.sq_sq_major_workspace(ct.byref(g), ct.byref(p), ct.byref(r), ct.byref(m), int(capacity))
+    if iws is None or iws.numel() < ineed:
+        iws = _workspace(ineed, dev)
+    gd = None if g_depth is None else _f32(g_depth, "g_depth")
+    gs = None if g_sem is None else _f32(g_sem, "g_sem")
+    L.check(lib.sq_render_bwd_sq_major(ct.byref(g), ct.byref(ix), ct.byref(p), ct.byref(r), ct.byref(m),
+                                       _ptr(ckpt), _ptr(gd), _ptr(gs), ct.byref(gr), int(capacity),
+                                       _ptr(out["interactions"]), _ptr(iws), iws.numel(), ct.byref(t), _ptr(wbuf),
+                                       wbuf.numel(), _stream_handle(stream)))
+    return out
+
+
 BWD_STAT_NAMES = ("samples1", "listed1", "eval1", "samples2", "listed2", "eval2")
 
 

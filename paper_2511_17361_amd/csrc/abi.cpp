@@ -353,7 +353,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 203; }
+int32_t sq_version(void) { return 204; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
@@ -484,6 +484,63 @@ sq_status sq_render_fwd_loss(const sq_grid* grid, const sq_index* idx, const sq_
     sq_tuning t = tuning ? *tuning : default_tuning();
     t.chunk = march->ckpt_every;
     return fwd_loss_checked(p, &io, weights, &t, ws, ws_bytes, stream);
+}
+
+size_t sq_sq_major_workspace(const sq_grid* grid, const sq_prims* prims, const sq_rays* rays, const sq_march* march,
+                             int64_t capacity) {
+    if (!grid_ok(grid) || !prims || !rays || !march || capacity < 0 || prims->n < 0 || prims->n_classes < 1 ||
+        prims->n_classes > SQ_MAX_CLASSES)
+        return 0;
+    sq_batch b;
+    one_scene(grid, march, prims->n, prims->n_classes, rays->n_cams, rays->height, rays->width, 0, b);
+    Plan p;
+    if (make_plan(&b, 8, p)) return 0;
+    return sqr::sq_major_workspace_bytes(p.g, p.d, to_dev(march, march->ckpt_every), capacity);
+}
+
+sq_status sq_render_bwd_sq_major(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
+                                 const sq_rays* rays, const sq_march* march, const float* ckpt,
+                                 const float* g_depth, const float* g_sem, const sq_grads* grads, int64_t capacity,
+                                 int64_t* interactions, void* iws, size_t iws_bytes, const sq_tuning* tuning,
+                                 void* ws, size_t ws_bytes, hipStream_t stream) {
+    sq_status s;
+    if ((s = check_grid(grid))) return s;
+    if ((s = check_index(idx, true))) return s;
+    if ((s = check_prims(prims, true))) return s;
+    if ((s = check_rays(rays))) return s;
+    if ((s = check_march(march))) return s;
+    if (!(march->ckpt_every == 4 || march->ckpt_every == 8 || march->ckpt_every == 16))
+        return fail(SQ_ERR_INVALID, "backward needs ckpt_every in {4, 8, 16} (got %d)", march->ckpt_every);
+    const int64_t nr = (int64_t)rays->n_cams * rays->height * rays->width;
+    if (nr > 0 && !ckpt) return fail(SQ_ERR_INVALID, "ckpt is NULL");
+    if (!grads) return fail(SQ_ERR_INVALID, "grads is NULL");
+    if (!interactions) return fail(SQ_ERR_INVALID, "interactions (device int64) is NULL");
+    if (capacity < 0 || capacity > ((int64_t)1 << 40)) return fail(SQ_ERR_INVALID, "capacity out of range");
+    if (nr * (int64_t)march->n_samples >= ((int64_t)1 << 32))
+        return fail(SQ_ERR_UNSUPPORTED, "rays x samples must stay below 2^32 for the interaction ids");
+    sqr::TuneDev tune;
+    if ((s = tuning_of(tuning, tune))) return s;
+    sq_batch b;
+    one_scene(grid, march, prims->n, prims->n_classes, rays->n_cams, rays->height, rays->width, idx->capacity, b);
+    Plan p;
+    if ((s = make_plan(&b, tune.tile_w, p))) return s;
+    sq_batch_io io;
+    io_from(idx, prims, rays, io);
+    io.ckpt = const_cast<float*>(ckpt);
+    io.g_depth = g_depth; io.g_sem = g_sem;
+    io.g_means = grads->means; io.g_quats = grads->quats; io.g_scales = grads->scales; io.g_eps = grads->eps;
+    io.g_opacity = grads->opacity; io.g_logits = grads->logits;
+    if (p.d.total_prims > 0 && (!io.g_means || !io.g_quats || !io.g_scales || !io.g_eps || !io.g_opacity ||
+                                !io.g_logits))
+        return fail(SQ_ERR_INVALID, "a gradient output array is NULL");
+    if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+    const sqr::MarchDev md = to_dev(march, march->ckpt_every);
+    const size_t need = sqr::sq_major_workspace_bytes(p.g, p.d, md, capacity);
+    if (!iws || iws_bytes < need) return fail(SQ_ERR_CAPACITY, "interaction workspace %zu < %zu bytes", iws_bytes, need);
+    if ((uintptr_t)iws % sqr::WS_ALIGN) return fail(SQ_ERR_INVALID, "interaction workspace must be 256-byte aligned");
+    const hipError_t e = sqr::launch_batch_bwd_sq_major(p.g, p.d, md, to_dev(&io), capacity, interactions, iws, tune,
+                                                        ws, stream);
+    return hip_status(e, "render_bwd_sq_major");
 }
 
 size_t sq_voxelise_workspace(const sq_grid* grid, const sq_prims* prims) {

@@ -1105,6 +1105,319 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
 }
 
 // ---------------------------------------------------------------------------
+// Superquadric-major backward (Sec. 3.3 "Backward Pass", Processes 1-3), an
+// alternative to the wavefront-reduced atomics of the default backward:
+//   1. per ray, replay the chunks from the checkpoints and store, per sample,
+//      dL/da_j and w_j (k_sqm_replay);
+//   2. build the (primitive, sample) interaction set from the index and group
+//      it by primitive: count per primitive, scan, scatter sample ids into
+//      contiguous per-primitive ranges (k_sqm_walk<false/true>, k_sqm_scan);
+//   3. one block per primitive reduces its range: every interaction is
+//      evaluated against the block's (uniform) record and the 15 + C sums are
+//      reduced in registers, across the wavefront and across the block, and
+//      written once -- no global atomics (k_sqm_reduce).
+// ---------------------------------------------------------------------------
+
+// dL/dp of one pair through p = exp(-f) to the accumulator row x (added).
+template <int VP>
+__device__ __forceinline__ void pair_grad_add(cf_ptr r, const PairEval& ev, const float dd[3], float da, float w,
+                                              float gam, float x[VP]) {
+    const float a_ = r[12], b_ = r[13], e_ = r[14], sig = r[15];
+    const float dp = fmaf(da, sig, w * gam);
+    const float df = -ev.p * dp;
+    const float invA = ev.A > 0.0f ? hw_rcp(ev.A) : 0.0f;
+    const float cu = df * e_ * a_ * ev.B * invA;
+    const float gu = ev.u != 0.0f ? cu * ev.X * hw_rcp(ev.u) : 0.0f;
+    const float gv = ev.v != 0.0f ? cu * ev.Y * hw_rcp(ev.v) : 0.0f;
+    const float gw = ev.w != 0.0f ? df * b_ * ev.Z * hw_rcp(ev.w) : 0.0f;
+    const float gx0 = gu * r[17], gx1 = gv * r[18], gx2 = gw * r[19];
+    const float lnA = ev.A > 0.0f ? ev.lA * LN2 : 0.0f;
+    const float XlU = ev.X > 0.0f ? ev.X * ev.lu * LN2 : 0.0f;
+    const float YlV = ev.Y > 0.0f ? ev.Y * ev.lv * LN2 : 0.0f;
+    const float ZlW = ev.Z > 0.0f ? ev.Z * ev.lw * LN2 : 0.0f;
+    const float dfde1 = -0.5f * e_ * b_ * ev.B * lnA - 0.5f * b_ * b_ * ZlW;
+    const float dfde2 = 0.5f * e_ * a_ * ev.B * (lnA - a_ * (XlU + YlV) * invA);
+    x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
+    x[A_E1] = fmaf(df, dfde1, x[A_E1]);
+    x[A_E2] = fmaf(df, dfde2, x[A_E2]);
+    x[A_XS + 0] += gx0; x[A_XS + 1] += gx1; x[A_XS + 2] += gx2;
+    x[A_R + 0] = fmaf(gx0, dd[0], x[A_R + 0]);
+    x[A_R + 1] = fmaf(gx0, dd[1], x[A_R + 1]);
+    x[A_R + 2] = fmaf(gx0, dd[2], x[A_R + 2]);
+    x[A_R + 3] = fmaf(gx1, dd[0], x[A_R + 3]);
+    x[A_R + 4] = fmaf(gx1, dd[1], x[A_R + 4]);
+    x[A_R + 5] = fmaf(gx1, dd[2], x[A_R + 5]);
+    x[A_R + 6] = fmaf(gx2, dd[0], x[A_R + 6]);
+    x[A_R + 7] = fmaf(gx2, dd[1], x[A_R + 7]);
+    x[A_R + 8] = fmaf(gx2, dd[2], x[A_R + 8]);
+}
+
+// Process 1: per sample dL/da_j (dA) and w_j (W), [rays x L], zero where the
+// sample is absent or contributes nothing.  Chunk replay as in the
+// sample-major backward (LDS per wave: a_j, T_j, G_j of one chunk).
+template <int CP>
+__device__ __forceinline__ void sqm_replay_tile(const Ctx& P, int s, int tile, float* sw, float* dA, float* W,
+                                                float* gSr) {
+    const SceneDev& S = P.desc->s[s];
+    const RayLane rl = setup_lane(P, S, tile);
+    const SceneIndex X = scene_index<CP>(P, s, S);
+    const int lane = threadIdx.x & 63;
+    const int K = P.mr.K, L = P.mr.L;
+    float* sm_a = sw;
+    float* sm_T = sw + K * 64;
+    float* sm_G = sw + 2 * K * 64;
+    const int64_t R = (int64_t)S.cams * S.H * S.W;
+    const int64_t HW = (int64_t)S.H * S.W;
+    const int nck = (L + K - 1) / K;
+    const float* ckpt = P.ckpt + (int64_t)nck * S.ray_off;
+    const float kappa = P.mr.kappa;
+    const int64_t ray = rl.valid ? lane_ray(rl, S) : 0;
+
+    const float gD = (rl.valid && P.g_depth) ? P.g_depth[ray] : 0.0f;
+    float gS[CP];
+    const int64_t gbase = S.ray_off * P.C + (int64_t)rl.cam * P.C * HW + lane_pix(rl, S);
+#pragma unroll
+    for (int c = 0; c < CP; ++c) gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[gbase + c * HW] : 0.0f;
+    if (rl.valid) {
+#pragma unroll
+        for (int c = 0; c < CP; ++c) gSr[ray * CP + c] = gS[c];     // ray-major copy for Process 3
+    }
+
+    float Q = 0.0f;
+    for (int ci = nck - 1; ci >= 0; --ci) {
+        const int j0 = ci * K;
+        const int jn = min(K, L - j0);
+        const float Tc = rl.valid ? ckpt[(int64_t)ci * R + lane_lray(rl, S)] : 0.0f;
+        if (wave_ballot((Tc > 0.0f) && (Tc >= kappa)) == 0) {
+            if (rl.valid)
+                for (int jj = 0; jj < jn; ++jj) { dA[ray * L + j0 + jj] = 0.0f; W[ray * L + j0 + jj] = 0.0f; }
+            continue;
+        }
+        float T = Tc;
+        for (int jj = 0; jj < jn; ++jj) {
+            const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
+                                               rl.dx, rl.dy, rl.dz);
+            int n = 0, f = 0;
+            const bool pres = (T > 0.0f) && (T >= kappa);
+            bool act = pres && (sp.v >= 0);
+            if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
+            float a = 0.0f, G = 0.0f;
+            bool pend = act;
+            uint64_t m;
+            while ((m = wave_ballot(pend)) != 0) {
+                const int leader = __builtin_ctzll(m);
+                const int v0 = readlane_i(sp.v, leader);
+                const int f0 = readlane_i(f, leader);
+                const int n0 = clamp_list(f0, readlane_i(n, leader), X.cap);
+                const bool mine = pend && (sp.v == v0);
+                if (mine) {
+                    for (int e = 0; e < n0; ++e) {
+                        const int k = X.ids[f0 + e];
+                        if ((unsigned)k >= (unsigned)X.n) continue;
+                        const cf_ptr r = X.rec + (size_t)k * REC;
+                        const float p = eval_p(r, sp.x, sp.y, sp.z);
+                        if (p != 0.0f) {
+                            a = fmaf(p, r[15], a);
+                            const cf_ptr lg = X.lgp + (size_t)k * CP;
+                            float gam = 0.0f;
+#pragma unroll
+                            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+                            G = fmaf(p, gam, G);
+                        }
+                    }
+                }
+                pend = pend && !mine;
+            }
+            sm_a[jj * 64 + lane] = a;
+            sm_T[jj * 64 + lane] = pres ? T : 0.0f;
+            sm_G[jj * 64 + lane] = fmaf(gD, sp.t, G);
+            T = T * (1.0f - fminf(a, 1.0f));
+        }
+        for (int jj = jn - 1; jj >= 0; --jj) {
+            const float a = sm_a[jj * 64 + lane];
+            const float Tj = sm_T[jj * 64 + lane];
+            const float G = sm_G[jj * 64 + lane];
+            const float alpha = fminf(a, 1.0f);
+            const float dalpha = Tj * (G - Q);
+            Q = fmaf(alpha, G, (1.0f - alpha) * Q);
+            if (rl.valid) {
+                dA[ray * L + j0 + jj] = (a < 1.0f) ? dalpha : 0.0f;
+                W[ray * L + j0 + jj] = Tj * alpha;
+            }
+        }
+    }
+}
+
+template <int CP>
+__global__ __launch_bounds__(256) void k_sqm_replay(Ctx P, float* dA, float* W, float* gSr) {
+    extern __shared__ float smem[];   // [wave][3][K][64]
+    float* sw = smem + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 3 * P.mr.K * 64;
+    for_each_tile<false>(P, [&](int t, const Ctx& Q) {
+        const int s = find_scene(Q.desc, t);
+        sqm_replay_tile<CP>(Q, s, t - Q.desc->s[s].tile_off, sw, dA, W, gSr);
+    });
+}
+
+// Process 2, voxel-major.  The index lists primitive k in voxel v exactly
+// when v lies in k's box, so k's interactions are the active samples (dL/da_j
+// or w_j nonzero) of the voxels of its box.  Samples are bucketed by voxel
+// (count, scan, scatter: one atomic per sample), then each primitive copies
+// the buckets of its box, in voxel order, into its contiguous range.
+// Single scene: the rays and voxels of scene 0.
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_sqm_bucket(Ctx P, const float* __restrict__ dA,
+                                                    const float* __restrict__ W, int* vcnt,
+                                                    const int64_t* __restrict__ voff, int* vcur, uint32_t* vsamp) {
+    const int L = P.mr.L;
+    const int64_t n = P.desc->total_rays * (int64_t)L;
+    for (int64_t sid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sid < n;
+         sid += (int64_t)gridDim.x * blockDim.x) {
+        if (dA[sid] == 0.0f && W[sid] == 0.0f) continue;
+        const int64_t ray = sid / L;
+        const int j = (int)(sid - ray * L);
+        const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j, P.origins[3 * ray],
+                                           P.origins[3 * ray + 1], P.origins[3 * ray + 2], P.dirs[3 * ray],
+                                           P.dirs[3 * ray + 1], P.dirs[3 * ray + 2]);
+        if (sp.v < 0 || P.counts[sp.v] == 0) continue;
+        if (!SCATTER) {
+            atomicAdd(&vcnt[sp.v], 1);
+        } else {
+            const int at = atomicAdd(&vcur[sp.v], 1);
+            vsamp[voff[sp.v] + at] = (uint32_t)sid;
+        }
+    }
+}
+
+// cnt[k] = number of active samples in the voxels of k's box.
+__global__ __launch_bounds__(256) void k_sqm_prim_count(Ctx P, const int* __restrict__ vcnt, int* cnt) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.desc->total_prims) return;
+    const float* r = P.rec + (size_t)k * REC;
+    const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+    int64_t c = 0;
+    if (bx != EMPTY_BOX)
+        for (int ix = bx & 0xffff; ix <= (bx >> 16); ++ix)
+            for (int iy = by & 0xffff; iy <= (by >> 16); ++iy) {
+                const int64_t v0 = ((int64_t)ix * P.g.Y + iy) * P.g.Z;
+                for (int iz = bz & 0xffff; iz <= (bz >> 16); ++iz) c += vcnt[v0 + iz];
+            }
+    cnt[k] = (int)min(c, (int64_t)INT_MAX);
+}
+
+// One block per primitive: copy the voxel buckets of its box into
+// pairs[off[k] ...], dropping entries at or beyond capacity.
+__global__ __launch_bounds__(256) void k_sqm_prim_fill(Ctx P, const int* __restrict__ vcnt,
+                                                       const int64_t* __restrict__ voff,
+                                                       const uint32_t* __restrict__ vsamp,
+                                                       const int64_t* __restrict__ off, uint32_t* pairs,
+                                                       int64_t capacity) {
+    const int k = blockIdx.x;
+    const float* r = P.rec + (size_t)k * REC;
+    const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+    if (bx == EMPTY_BOX) return;
+    int64_t pos = off[k];
+    for (int ix = bx & 0xffff; ix <= (bx >> 16); ++ix)
+        for (int iy = by & 0xffff; iy <= (by >> 16); ++iy) {
+            const int64_t v0 = ((int64_t)ix * P.g.Y + iy) * P.g.Z;
+            for (int iz = bz & 0xffff; iz <= (bz >> 16); ++iz) {
+                const int nv = vcnt[v0 + iz];
+                const int64_t src = voff[v0 + iz];
+                for (int e = threadIdx.x; e < nv; e += blockDim.x)
+                    if (pos + e < capacity) pairs[pos + e] = vsamp[src + e];
+                pos += nv;
+            }
+        }
+}
+
+// Exclusive scan of the per-primitive counts into int64 offsets [n + 1]; one
+// block; *total = off[n].
+__global__ __launch_bounds__(1024) void k_sqm_scan(int n, const int* __restrict__ cnt, int64_t* off,
+                                                   int64_t* total) {
+    __shared__ int64_t part[1024];
+    int64_t carry = 0;
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int64_t v = i < n ? cnt[i] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const int64_t add = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < n) off[i] = carry + part[threadIdx.x] - v;
+        carry += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        off[n] = carry;
+        *total = carry;
+    }
+}
+
+// Process 3: one block per primitive reduces its interaction range.
+template <int CP>
+__global__ __launch_bounds__(256) void k_sqm_reduce(Ctx P, const float* __restrict__ dA, const float* __restrict__ W,
+                                                    const float* __restrict__ gSr, const int64_t* __restrict__ off,
+                                                    const uint32_t* __restrict__ pairs, int64_t capacity) {
+    constexpr int VP = AccRow<CP>::P;
+    constexpr int V = AccRow<CP>::V;
+    __shared__ float red[4][VP];
+    const int kg = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int s = 0;
+    for (int i = 1; i < P.desc->n_scenes; ++i) s += (kg >= P.desc->s[i].prim_off) ? 1 : 0;
+    const SceneDev& S = P.desc->s[s];
+    const cf_ptr r = as_const(P.rec) + (size_t)kg * REC;
+    const cf_ptr lg = as_const(P.lgp) + (size_t)kg * CP;
+    const int L = P.mr.L;
+    const int64_t lo = off[kg], hi = min(off[kg + 1], capacity);
+    float x[VP];
+#pragma unroll
+    for (int i = 0; i < VP; ++i) x[i] = 0.0f;
+    float om = 0.0f;     // sum of w p over the range, for the logits
+    float gsum[CP];      // sum of w p g_S per class
+#pragma unroll
+    for (int c = 0; c < CP; ++c) gsum[c] = 0.0f;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint32_t sid = pairs[i];
+        const int64_t ray = sid / (uint32_t)L;
+        const int j = (int)(sid - (uint32_t)ray * (uint32_t)L);
+        const float da = dA[sid], w = W[sid];
+        const float ox = P.origins[3 * ray], oy = P.origins[3 * ray + 1], oz = P.origins[3 * ray + 2];
+        const float dx = P.dirs[3 * ray], dy = P.dirs[3 * ray + 1], dz = P.dirs[3 * ray + 2];
+        const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j, ox, oy, oz, dx, dy, dz);
+        PairEval ev;
+        float dd[3];
+        if (!eval_pair(r, sp.x, sp.y, sp.z, dd, ev) || !(ev.p > 0.0f)) continue;
+        float gam = 0.0f;
+        const float wp = w * ev.p;
+#pragma unroll
+        for (int c = 0; c < CP; ++c) {
+            const float g = gSr[ray * CP + c];
+            gam = fmaf(g, lg[c], gam);
+            gsum[c] = fmaf(wp, g, gsum[c]);
+        }
+        pair_grad_add<VP>(r, ev, dd, da, w, gam, x);
+        om += wp;
+    }
+#pragma unroll
+    for (int c = 0; c < CP; ++c) x[A_LG + c] = gsum[c];
+    (void)om;
+    const float tot = transpose_reduce<VP>(x, lane);
+    constexpr int shift = 6 - Log2<VP>::v;
+    const int vi = lane >> shift;
+    if ((lane & ((1 << shift) - 1)) == 0 && vi < VP) red[wave][vi] = tot;
+    __syncthreads();
+    if ((int)threadIdx.x < VP) {
+        const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        P.acc[(size_t)kg * VP + threadIdx.x] = (int)threadIdx.x < V ? v : 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Finalize: accumulator row -> parameter gradients
 //   g_m = -R^T sum(g_xs);  g_s_i = -(1/s_i) [G_R R^T]_ii  (G_R = sum g_xs (x-m)^T)
 //   g_q = (I - q^ q^T)/|q| * sum_ij G_R_ij dR_ij/dq^
@@ -1265,6 +1578,14 @@ static void launch_tiles(Kern k, bool persistent, const Ctx& P, int wpb, size_t 
     hipLaunchKernelGGL(k, dim3(blocks), block, shm, st, P);
 }
 
+// One wave per tile on a static grid, with extra kernel arguments after the context.
+template <typename Kern, typename... A>
+static void launch_tiles_with(Kern k, const Ctx& P, int wpb, size_t shm, hipStream_t st, A... args) {
+    const int static_blocks = (P.total_tiles + wpb - 1) / wpb;
+    if (static_blocks == 0) return;
+    hipLaunchKernelGGL(k, dim3(static_blocks), dim3(64 * wpb), shm, st, P, args...);
+}
+
 template <int CP>
 static void prep_records(const BatchDesc& d, const GridDev& g, const BatchIO& io, const WsLayout& l,
                          hipStream_t st) {
@@ -1383,6 +1704,106 @@ hipError_t launch_batch_voxelise(const GridDev& g, const BatchDesc& d, const Bat
         case 8: vox_run<8>(g, d, io, l, P, st); break;
         case 17: vox_run<17>(g, d, io, l, P, st); break;
         default: vox_run<32>(g, d, io, l, P, st); break;
+    }
+    return hipGetLastError();
+}
+
+// ---- superquadric-major backward ------------------------------------------
+// Interaction workspace (caller's): dA, W [rays x L] float; cnt [prims] int;
+// off [prims + 1] int64; cur [prims] uint64; pairs [capacity + 1] uint32 (the
+// last slot is a write sink for lanes without an interaction).
+struct SqmLayout {
+    float *dA, *W, *gSr;
+    int *vcnt, *vcur;
+    int64_t* voff;
+    uint32_t* vsamp;
+    int* cnt;
+    int64_t* off;
+    uint32_t* pairs;
+};
+
+static SqmLayout carve_sqm(void* iws, const GridDev& g, const BatchDesc& d, const MarchDev& mr, int64_t capacity,
+                           size_t* bytes) {
+    const int64_t V = (int64_t)g.X * g.Y * g.Z;
+    const int64_t S = d.total_rays * (int64_t)mr.L;
+    const size_t s_dw = align_up((size_t)S * sizeof(float));
+    const size_t s_gs = align_up((size_t)d.total_rays * padded_classes(d.C) * sizeof(float));
+    const size_t s_vc = align_up((size_t)V * sizeof(int));
+    const size_t s_vo = align_up(((size_t)V + 1) * sizeof(int64_t));
+    const size_t s_vs = align_up((size_t)S * sizeof(uint32_t));
+    const size_t s_cnt = align_up((size_t)d.total_prims * sizeof(int));
+    const size_t s_off = align_up(((size_t)d.total_prims + 1) * sizeof(int64_t));
+    const size_t s_pairs = align_up(((size_t)capacity + 1) * sizeof(uint32_t));
+    if (bytes) *bytes = 2 * s_dw + s_gs + 2 * s_vc + s_vo + s_vs + s_cnt + s_off + s_pairs;
+    SqmLayout l{};
+    char* p = (char*)iws;
+    if (!p) return l;
+    l.dA = (float*)p; p += s_dw;
+    l.W = (float*)p; p += s_dw;
+    l.gSr = (float*)p; p += s_gs;
+    l.vcnt = (int*)p; p += s_vc;
+    l.vcur = (int*)p; p += s_vc;
+    l.voff = (int64_t*)p; p += s_vo;
+    l.vsamp = (uint32_t*)p; p += s_vs;
+    l.cnt = (int*)p; p += s_cnt;
+    l.off = (int64_t*)p; p += s_off;
+    l.pairs = (uint32_t*)p;
+    return l;
+}
+
+size_t sq_major_workspace_bytes(const GridDev& g, const BatchDesc& d, const MarchDev& mr, int64_t capacity) {
+    size_t b = 0;
+    carve_sqm(nullptr, g, d, mr, capacity, &b);
+    return b;
+}
+
+template <int CP>
+static void sqm_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P,
+                    const SqmLayout& q, int64_t capacity, int64_t* total, int wpb, hipStream_t st) {
+    prep_records<CP>(d, g, io, l, st);
+    const int n = d.total_prims;
+    const int V = g.X * g.Y * g.Z;
+    const int64_t S = d.total_rays * (int64_t)P.mr.L;
+    const unsigned sblocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((S + 255) / 256, 8192));
+    const size_t shm = (size_t)wpb * 3 * P.mr.K * 64 * sizeof(float);
+    launch_tiles_with(k_sqm_replay<CP>, P, wpb, shm, st, q.dA, q.W, q.gSr);                   // Process 1
+    // Process 2: samples bucketed by voxel, then gathered per primitive box
+    hipLaunchKernelGGL(k_fill, dim3((V + 255) / 256), dim3(256), 0, st, (float*)q.vcnt, (int64_t)V, 0.0f);
+    hipLaunchKernelGGL(k_fill, dim3((V + 255) / 256), dim3(256), 0, st, (float*)q.vcur, (int64_t)V, 0.0f);
+    hipLaunchKernelGGL(k_sqm_bucket<false>, dim3(sblocks), dim3(256), 0, st, P, (const float*)q.dA,
+                       (const float*)q.W, q.vcnt, (const int64_t*)q.voff, q.vcur, q.vsamp);
+    hipLaunchKernelGGL(k_sqm_scan, dim3(1), dim3(1024), 0, st, V, (const int*)q.vcnt, q.voff, q.voff + V);
+    hipLaunchKernelGGL(k_sqm_bucket<true>, dim3(sblocks), dim3(256), 0, st, P, (const float*)q.dA,
+                       (const float*)q.W, q.vcnt, (const int64_t*)q.voff, q.vcur, q.vsamp);
+    if (n > 0)
+        hipLaunchKernelGGL(k_sqm_prim_count, dim3((n + 255) / 256), dim3(256), 0, st, P, (const int*)q.vcnt, q.cnt);
+    hipLaunchKernelGGL(k_sqm_scan, dim3(1), dim3(1024), 0, st, n, (const int*)q.cnt, q.off, total);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_sqm_prim_fill, dim3((unsigned)n), dim3(256), 0, st, P, (const int*)q.vcnt,
+                           (const int64_t*)q.voff, (const uint32_t*)q.vsamp, (const int64_t*)q.off, q.pairs,
+                           capacity);
+        hipLaunchKernelGGL(k_sqm_reduce<CP>, dim3((unsigned)n), dim3(256), 0, st, P, (const float*)q.dA,
+                           (const float*)q.W, (const float*)q.gSr, (const int64_t*)q.off,
+                           (const uint32_t*)q.pairs, capacity);                                      // Process 3
+        hipLaunchKernelGGL(k_finalize<CP>, dim3((n + 255) / 256), dim3(256), 0, st, n, d.C, io.quats, io.scales,
+                           (const float*)l.acc, io.g_means, io.g_quats, io.g_scales, io.g_eps, io.g_opacity,
+                           io.g_logits);
+    }
+}
+
+hipError_t launch_batch_bwd_sq_major(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
+                                     int64_t capacity, int64_t* total, void* iws, const TuneDev& tune, void* ws,
+                                     hipStream_t st) {
+    const WsLayout l = carve_ws(ws, g, d);
+    put_desc(d, l.desc, st);
+    const SqmLayout q = carve_sqm(iws, g, d, mr, capacity, nullptr);
+    Ctx P = make_ctx(g, d, mr, io, l, nullptr);
+    const int wpb = tune.waves_per_block;
+    switch (padded_classes(d.C)) {
+        case 4: sqm_run<4>(g, d, io, l, P, q, capacity, total, wpb, st); break;
+        case 8: sqm_run<8>(g, d, io, l, P, q, capacity, total, wpb, st); break;
+        case 17: sqm_run<17>(g, d, io, l, P, q, capacity, total, wpb, st); break;
+        default: sqm_run<32>(g, d, io, l, P, q, capacity, total, wpb, st); break;
     }
     return hipGetLastError();
 }

@@ -99,6 +99,13 @@ hipError_t launch_batch_bwd(const GridDev& g, const BatchDesc& d, const MarchDev
 hipError_t launch_batch_voxelise(const GridDev& g, const BatchDesc& d, const BatchIO& io, float tau, void* ws,
                                  hipStream_t st);
 
+// Superquadric-major backward (interaction sort by primitive); `iws` is the
+// caller's interaction workspace of sq_major_workspace_bytes(d, mr, capacity).
+size_t sq_major_workspace_bytes(const GridDev& g, const BatchDesc& d, const MarchDev& mr, int64_t capacity);
+hipError_t launch_batch_bwd_sq_major(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,
+                                     int64_t capacity, int64_t* total, void* iws, const TuneDev& tune, void* ws,
+                                     hipStream_t st);
+
 // whether the primitive-major backward applies to these arguments
 bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb);
 
