@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_count_labels(int64_t n, int C, const in
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         ns += (unsigned)sem_label[i] < (unsigned)C ? 1 : 0;
         const float dl = depth_label[i];
-        nd += (dl > 0.0f) & (dl < INFINITY) ? 1 : 0;
+        nd += ((dl > 0.0f) && (dl < INFINITY)) ? 1 : 0;
     }
     ns = wave_sum_int(ns);
     nd = wave_sum_int(nd);
@@ -687,6 +687,76 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of one (sample, primitive) pair through p = exp(-f) (Eq.
+// eq:sq_occupancy_prob with f of Sec. "SuperQuadrics"), added to an
+// accumulator row WITHOUT the primitive's constant factors; k_finalize
+// multiplies each row entry by its factor once per primitive (acc_factor).
+// With dfn = p dL/dp = -dL/df, Bs = B / ln 2, Zs = Z / ln 2 and base-2 logs:
+//   x[A_SIG]      += dL/da_j p                         (factor 1)
+//   x[A_E1]       += dfn (e Bs log2 A + b Zs log2|w|)  (factor  ln2^2 b / 2)
+//   x[A_E2]       += dfn (Bs log2 A - a Bs/A S)        (factor -ln2^2 e a / 2)
+//                    S = X log2|u| + Y log2|v|
+//   g = dfn (Bs/A X/u, Bs/A Y/v, Zs/w)                 (factors -ln2 e a/s_x,
+//   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c         -ln2 e a/s_y, -ln2 b/s_z)
+// A zero |u|, |v|, |w| or A has log2 = -inf next to a zero power; the logs are
+// clamped to -FLT_MAX so those products are exactly 0 (their limit), and A is
+// clamped to FLT_MIN inside the reciprocal (Bs is 0 there).  The derivative
+// along an axis where the coordinate is exactly 0 is taken as 0.
+// ---------------------------------------------------------------------------
+// Clamps on the float bits, one integer op each (fmaxf would add canonicalising
+// maxes): as unsigned integers, -inf (0xff800000) is the only non-NaN float
+// above -FLT_MAX (0xff7fffff), and non-negative floats order like their bits.
+__device__ __forceinline__ float finite_below(float x) {
+    return __uint_as_float(min(__float_as_uint(x), 0xff7fffffu));
+}
+__device__ __forceinline__ float at_least_flt_min(float x_nonneg) {
+    return __uint_as_float(max(__float_as_uint(x_nonneg), 0x00800000u));
+}
+
+template <int VP>
+__device__ __forceinline__ void pair_adjoint(cf_ptr r, const PairEval& ev, const float dd[3], float dfn, float da,
+                                             float x[VP]) {
+    const float a_ = r[12], b_ = r[13], e_ = r[14];
+    const float bia = ev.Bs * hw_rcp(at_least_flt_min(ev.A));
+    const float db = dfn * bia;
+    const float g0 = ev.u != 0.0f ? db * (ev.X * hw_rcp(ev.u)) : 0.0f;
+    const float g1 = ev.v != 0.0f ? db * (ev.Y * hw_rcp(ev.v)) : 0.0f;
+    const float g2 = ev.w != 0.0f ? dfn * (ev.Zs * hw_rcp(ev.w)) : 0.0f;
+    const float lA = finite_below(ev.lA), lu = finite_below(ev.lu);
+    const float lv = finite_below(ev.lv), lw = finite_below(ev.lw);
+    const float bla = ev.Bs * lA;
+    const float S = fmaf(ev.X, lu, ev.Y * lv);
+    x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
+    x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * (ev.Zs * lw)), x[A_E1]);
+    x[A_E2] = fmaf(dfn, fmaf(-a_, bia * S, bla), x[A_E2]);
+    x[A_XS + 0] += g0; x[A_XS + 1] += g1; x[A_XS + 2] += g2;
+    x[A_R + 0] = fmaf(g0, dd[0], x[A_R + 0]);
+    x[A_R + 1] = fmaf(g0, dd[1], x[A_R + 1]);
+    x[A_R + 2] = fmaf(g0, dd[2], x[A_R + 2]);
+    x[A_R + 3] = fmaf(g1, dd[0], x[A_R + 3]);
+    x[A_R + 4] = fmaf(g1, dd[1], x[A_R + 4]);
+    x[A_R + 5] = fmaf(g1, dd[2], x[A_R + 5]);
+    x[A_R + 6] = fmaf(g2, dd[0], x[A_R + 6]);
+    x[A_R + 7] = fmaf(g2, dd[1], x[A_R + 7]);
+    x[A_R + 8] = fmaf(g2, dd[2], x[A_R + 8]);
+}
+
+// The constant factor of accumulator entry vi of primitive record r (see
+// pair_adjoint); 1 for the opacity and the logits.
+__device__ __forceinline__ float acc_factor(cf_ptr r, int vi) {
+    const float a_ = r[12], b_ = r[13], e_ = r[14];
+    const float fu = -LN2 * e_ * a_;
+    if (vi == A_E1) return 0.5f * LN2 * LN2 * b_;
+    if (vi == A_E2) return -0.5f * LN2 * LN2 * e_ * a_;
+    if (vi >= A_XS && vi < A_XS + 3) return vi == A_XS + 2 ? -LN2 * b_ * r[19] : fu * r[17 + vi - A_XS];
+    if (vi >= A_R && vi < A_R + 9) {
+        const int i = (vi - A_R) / 3;
+        return i == 2 ? -LN2 * b_ * r[19] : fu * r[17 + i];
+    }
+    return 1.0f;
+}
+
+// ---------------------------------------------------------------------------
 // Backward, sample-major (fallback): one reduction per (sample, primitive)
 // ---------------------------------------------------------------------------
 template <int CP, bool STATS>
@@ -813,31 +883,11 @@ __device__ __forceinline__ void bwd_sm_tile(const Ctx& P, int s, int tile, float
                         if (STATS && kept) st[5] += 1;
                         if (kept && ev.p > 0.0f) {
                             any = true;
-                            const float a_ = r[12], b_ = r[13], e_ = r[14], sig = r[15];
                             float gam = 0.0f;
 #pragma unroll
                             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
-                            const float dp = fmaf(da, sig, w * gam);
-                            const float df = -ev.p * dp;
-                            const float invA = ev.A > 0.0f ? hw_rcp(ev.A) : 0.0f;
-                            const float cu = df * e_ * a_ * ev.B * invA;
-                            const float gu = ev.u != 0.0f ? cu * ev.X * hw_rcp(ev.u) : 0.0f;
-                            const float gv = ev.v != 0.0f ? cu * ev.Y * hw_rcp(ev.v) : 0.0f;
-                            const float gw = ev.w != 0.0f ? df * b_ * ev.Z * hw_rcp(ev.w) : 0.0f;
-                            const float gx0 = gu * r[17], gx1 = gv * r[18], gx2 = gw * r[19];
-                            const float lnA = ev.A > 0.0f ? ev.lA * LN2 : 0.0f;
-                            const float XlU = ev.X > 0.0f ? ev.X * ev.lu * LN2 : 0.0f;
-                            const float YlV = ev.Y > 0.0f ? ev.Y * ev.lv * LN2 : 0.0f;
-                            const float ZlW = ev.Z > 0.0f ? ev.Z * ev.lw * LN2 : 0.0f;
-                            const float dfde1 = -0.5f * e_ * b_ * ev.B * lnA - 0.5f * b_ * b_ * ZlW;
-                            const float dfde2 = 0.5f * e_ * a_ * ev.B * (lnA - a_ * (XlU + YlV) * invA);
-                            x[A_SIG] = da * ev.p;
-                            x[A_E1] = df * dfde1;
-                            x[A_E2] = df * dfde2;
-                            x[A_XS + 0] = gx0; x[A_XS + 1] = gx1; x[A_XS + 2] = gx2;
-                            x[A_R + 0] = gx0 * dd[0]; x[A_R + 1] = gx0 * dd[1]; x[A_R + 2] = gx0 * dd[2];
-                            x[A_R + 3] = gx1 * dd[0]; x[A_R + 4] = gx1 * dd[1]; x[A_R + 5] = gx1 * dd[2];
-                            x[A_R + 6] = gx2 * dd[0]; x[A_R + 7] = gx2 * dd[1]; x[A_R + 8] = gx2 * dd[2];
+                            const float dfn = ev.p * fmaf(da, r[15], w * gam);
+                            pair_adjoint<VP>(r, ev, dd, dfn, da, x);
                             wp = w * ev.p;
                         }
                     }
@@ -1032,7 +1082,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             float gam = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
-            const float a_ = r[12], b_ = r[13], e_ = r[14], sig = r[15];
+            const float sig = r[15];
             float x[VP];
 #pragma unroll
             for (int i = 0; i < VP; ++i) x[i] = 0.0f;
@@ -1048,33 +1098,8 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                     if (kept && ev.p > 0.0f) {
                         contrib = true;
                         const float da = a[jj], w = G[jj];
-                        const float dp = fmaf(da, sig, w * gam);
-                        const float df = -ev.p * dp;
-                        const float invA = ev.A > 0.0f ? hw_rcp(ev.A) : 0.0f;
-                        const float cu = df * e_ * a_ * ev.B * invA;
-                        const float gu = ev.u != 0.0f ? cu * ev.X * hw_rcp(ev.u) : 0.0f;
-                        const float gv = ev.v != 0.0f ? cu * ev.Y * hw_rcp(ev.v) : 0.0f;
-                        const float gw = ev.w != 0.0f ? df * b_ * ev.Z * hw_rcp(ev.w) : 0.0f;
-                        const float gx0 = gu * r[17], gx1 = gv * r[18], gx2 = gw * r[19];
-                        const float lnA = ev.A > 0.0f ? ev.lA * LN2 : 0.0f;
-                        const float XlU = ev.X > 0.0f ? ev.X * ev.lu * LN2 : 0.0f;
-                        const float YlV = ev.Y > 0.0f ? ev.Y * ev.lv * LN2 : 0.0f;
-                        const float ZlW = ev.Z > 0.0f ? ev.Z * ev.lw * LN2 : 0.0f;
-                        const float dfde1 = -0.5f * e_ * b_ * ev.B * lnA - 0.5f * b_ * b_ * ZlW;
-                        const float dfde2 = 0.5f * e_ * a_ * ev.B * (lnA - a_ * (XlU + YlV) * invA);
-                        x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
-                        x[A_E1] = fmaf(df, dfde1, x[A_E1]);
-                        x[A_E2] = fmaf(df, dfde2, x[A_E2]);
-                        x[A_XS + 0] += gx0; x[A_XS + 1] += gx1; x[A_XS + 2] += gx2;
-                        x[A_R + 0] = fmaf(gx0, dd[0], x[A_R + 0]);
-                        x[A_R + 1] = fmaf(gx0, dd[1], x[A_R + 1]);
-                        x[A_R + 2] = fmaf(gx0, dd[2], x[A_R + 2]);
-                        x[A_R + 3] = fmaf(gx1, dd[0], x[A_R + 3]);
-                        x[A_R + 4] = fmaf(gx1, dd[1], x[A_R + 4]);
-                        x[A_R + 5] = fmaf(gx1, dd[2], x[A_R + 5]);
-                        x[A_R + 6] = fmaf(gx2, dd[0], x[A_R + 6]);
-                        x[A_R + 7] = fmaf(gx2, dd[1], x[A_R + 7]);
-                        x[A_R + 8] = fmaf(gx2, dd[2], x[A_R + 8]);
+                        const float dfn = ev.p * fmaf(da, sig, w * gam);
+                        pair_adjoint<VP>(r, ev, dd, dfn, da, x);
                         om = fmaf(w, ev.p, om);
                     }
                 }
@@ -1117,40 +1142,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
 //      reduced in registers, across the wavefront and across the block, and
 //      written once -- no global atomics (k_sqm_reduce).
 // ---------------------------------------------------------------------------
-
-// dL/dp of one pair through p = exp(-f) to the accumulator row x (added).
-template <int VP>
-__device__ __forceinline__ void pair_grad_add(cf_ptr r, const PairEval& ev, const float dd[3], float da, float w,
-                                              float gam, float x[VP]) {
-    const float a_ = r[12], b_ = r[13], e_ = r[14], sig = r[15];
-    const float dp = fmaf(da, sig, w * gam);
-    const float df = -ev.p * dp;
-    const float invA = ev.A > 0.0f ? hw_rcp(ev.A) : 0.0f;
-    const float cu = df * e_ * a_ * ev.B * invA;
-    const float gu = ev.u != 0.0f ? cu * ev.X * hw_rcp(ev.u) : 0.0f;
-    const float gv = ev.v != 0.0f ? cu * ev.Y * hw_rcp(ev.v) : 0.0f;
-    const float gw = ev.w != 0.0f ? df * b_ * ev.Z * hw_rcp(ev.w) : 0.0f;
-    const float gx0 = gu * r[17], gx1 = gv * r[18], gx2 = gw * r[19];
-    const float lnA = ev.A > 0.0f ? ev.lA * LN2 : 0.0f;
-    const float XlU = ev.X > 0.0f ? ev.X * ev.lu * LN2 : 0.0f;
-    const float YlV = ev.Y > 0.0f ? ev.Y * ev.lv * LN2 : 0.0f;
-    const float ZlW = ev.Z > 0.0f ? ev.Z * ev.lw * LN2 : 0.0f;
-    const float dfde1 = -0.5f * e_ * b_ * ev.B * lnA - 0.5f * b_ * b_ * ZlW;
-    const float dfde2 = 0.5f * e_ * a_ * ev.B * (lnA - a_ * (XlU + YlV) * invA);
-    x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
-    x[A_E1] = fmaf(df, dfde1, x[A_E1]);
-    x[A_E2] = fmaf(df, dfde2, x[A_E2]);
-    x[A_XS + 0] += gx0; x[A_XS + 1] += gx1; x[A_XS + 2] += gx2;
-    x[A_R + 0] = fmaf(gx0, dd[0], x[A_R + 0]);
-    x[A_R + 1] = fmaf(gx0, dd[1], x[A_R + 1]);
-    x[A_R + 2] = fmaf(gx0, dd[2], x[A_R + 2]);
-    x[A_R + 3] = fmaf(gx1, dd[0], x[A_R + 3]);
-    x[A_R + 4] = fmaf(gx1, dd[1], x[A_R + 4]);
-    x[A_R + 5] = fmaf(gx1, dd[2], x[A_R + 5]);
-    x[A_R + 6] = fmaf(gx2, dd[0], x[A_R + 6]);
-    x[A_R + 7] = fmaf(gx2, dd[1], x[A_R + 7]);
-    x[A_R + 8] = fmaf(gx2, dd[2], x[A_R + 8]);
-}
 
 // Process 1: per sample dL/da_j (dA) and w_j (W), [rays x L], zero where the
 // sample is absent or contributes nothing.  Chunk replay as in the
@@ -1400,7 +1391,7 @@ __global__ __launch_bounds__(256) void k_sqm_reduce(Ctx P, const float* __restri
             gam = fmaf(g, lg[c], gam);
             gsum[c] = fmaf(wp, g, gsum[c]);
         }
-        pair_grad_add<VP>(r, ev, dd, da, w, gam, x);
+        pair_adjoint<VP>(r, ev, dd, ev.p * fmaf(da, r[15], w * gam), da, x);
         om += wp;
     }
 #pragma unroll
@@ -1424,13 +1415,17 @@ __global__ __launch_bounds__(256) void k_sqm_reduce(Ctx P, const float* __restri
 // ---------------------------------------------------------------------------
 template <int CP>
 __global__ __launch_bounds__(256) void k_finalize(int n_total, int C, const float* __restrict__ quats,
-                                                  const float* __restrict__ scales, const float* __restrict__ acc,
-                                                  float* g_means, float* g_quats, float* g_scales, float* g_eps,
-                                                  float* g_opacity, float* g_logits) {
+                                                  const float* __restrict__ scales, const float* __restrict__ rec,
+                                                  const float* __restrict__ acc, float* g_means, float* g_quats,
+                                                  float* g_scales, float* g_eps, float* g_opacity,
+                                                  float* g_logits) {
     constexpr int VP = AccRow<CP>::P;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_total) return;
-    const float* a = acc + (size_t)k * VP;
+    // the accumulated sums carry no per-primitive constant factors (pair_adjoint)
+    const cf_ptr r = as_const(rec) + (size_t)k * REC;
+    float a[A_LG];
+    for (int i = 0; i < A_LG; ++i) a[i] = acc[(size_t)k * VP + i] * acc_factor(r, i);
     const float q0 = quats[4 * k], q1 = quats[4 * k + 1], q2 = quats[4 * k + 2], q3 = quats[4 * k + 3];
     const float qn = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
     const float w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
@@ -1461,7 +1456,7 @@ __global__ __launch_bounds__(256) void k_finalize(int n_total, int C, const floa
     g_eps[2 * k] = a[A_E1];
     g_eps[2 * k + 1] = a[A_E2];
     g_opacity[k] = a[A_SIG];
-    for (int c = 0; c < C; ++c) g_logits[(size_t)k * C + c] = a[A_LG + c];
+    for (int c = 0; c < C; ++c) g_logits[(size_t)k * C + c] = acc[(size_t)k * VP + A_LG + c];
 }
 
 // ---------------------------------------------------------------------------
@@ -1786,8 +1781,8 @@ static void sqm_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
                            (const float*)q.W, (const float*)q.gSr, (const int64_t*)q.off,
                            (const uint32_t*)q.pairs, capacity);                                      // Process 3
         hipLaunchKernelGGL(k_finalize<CP>, dim3((n + 255) / 256), dim3(256), 0, st, n, d.C, io.quats, io.scales,
-                           (const float*)l.acc, io.g_means, io.g_quats, io.g_scales, io.g_eps, io.g_opacity,
-                           io.g_logits);
+                           (const float*)l.rec, (const float*)l.acc, io.g_means, io.g_quats, io.g_scales,
+                           io.g_eps, io.g_opacity, io.g_logits);
     }
 }
 
@@ -1851,8 +1846,8 @@ static void bwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
     }
     if (d.total_prims > 0)
         hipLaunchKernelGGL(k_finalize<CP>, dim3((d.total_prims + 255) / 256), dim3(256), 0, st, d.total_prims, d.C,
-                           io.quats, io.scales, (const float*)l.acc, io.g_means, io.g_quats, io.g_scales, io.g_eps,
-                           io.g_opacity, io.g_logits);
+                           io.quats, io.scales, (const float*)l.rec, (const float*)l.acc, io.g_means,
+                           io.g_quats, io.g_scales, io.g_eps, io.g_opacity, io.g_logits);
 }
 
 hipError_t launch_batch_bwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,

@@ -107,11 +107,19 @@ __device__ __forceinline__ int pinned_centre_axis(float m, float lo, float inv, 
 struct PairEval {
     float u, v, w;         // canonical coordinates x_S / s
     float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
-    float X, Y, Z, A, lA, B;
+    float X, Y, A, lA;     // |u|^a, |v|^a, A = X + Y, log2 A
+    float Bs, Zs;          // A^e / ln 2, |w|^b / ln 2
     float p;
 };
 
-// Returns false when the pair is culled (float32 exp(-f) would be exactly 0).
+// log2(1 / ln 2): 2^(x + L2_LOG2E) = 2^x / ln 2
+constexpr float L2_LOG2E = 0.5287663729448977f;
+
+// Evaluation for the adjoint.  B and Z are carried divided by ln 2 (one FMA
+// each instead of a multiply), so p = 2^-(Bs + Zs) needs no extra scaling;
+// the adjoint's per-primitive factors absorb the ln 2.  p may differ from
+// eval_p's in the last bit.  Returns false when the pair is culled (float32
+// exp(-f) would be exactly 0).
 __device__ __forceinline__ bool eval_pair(cf_ptr rec, float x, float y, float z,
                                           float dxyz[3], PairEval& e) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
@@ -128,12 +136,11 @@ __device__ __forceinline__ bool eval_pair(cf_ptr rec, float x, float y, float z,
     const float a = rec[12], b = rec[13], ee = rec[14];
     e.X = hw_exp2(a * e.lu);
     e.Y = hw_exp2(a * e.lv);
-    e.Z = hw_exp2(b * e.lw);
+    e.Zs = hw_exp2(fmaf(b, e.lw, L2_LOG2E));
     e.A = e.X + e.Y;
     e.lA = hw_log2(e.A);
-    e.B = hw_exp2(ee * e.lA);
-    const float f = e.B + e.Z;
-    e.p = hw_exp2(-LOG2E * f);
+    e.Bs = hw_exp2(fmaf(ee, e.lA, L2_LOG2E));
+    e.p = hw_exp2(-(e.Bs + e.Zs));
     return true;
 }
 
