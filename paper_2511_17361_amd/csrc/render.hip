@@ -698,36 +698,28 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
 //                    S = X log2|u| + Y log2|v|
 //   g = dfn (Bs/A X/u, Bs/A Y/v, Zs/w)                 (factors -ln2 e a/s_x,
 //   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c         -ln2 e a/s_y, -ln2 b/s_z)
-// A zero |u|, |v|, |w| or A has log2 = -inf next to a zero power; the logs are
-// clamped to -FLT_MAX so those products are exactly 0 (their limit), and A is
-// clamped to FLT_MIN inside the reciprocal (Bs is 0 there).  The derivative
-// along an axis where the coordinate is exactly 0 is taken as 0.
+// Where |u|, |v|, |w| or A is 0 its log2 and reciprocal are infinite, but the
+// power they multiply (X, Y, Zs, Bs) is then exactly 0, and so is the limit of
+// the product; those products use the legacy multiply (0 x anything = 0), so
+// no compare or select is needed.  In particular the derivative along an axis
+// where the coordinate is exactly 0 comes out as 0.
 // ---------------------------------------------------------------------------
-// Clamps on the float bits, one integer op each (fmaxf would add canonicalising
-// maxes): as unsigned integers, -inf (0xff800000) is the only non-NaN float
-// above -FLT_MAX (0xff7fffff), and non-negative floats order like their bits.
-__device__ __forceinline__ float finite_below(float x) {
-    return __uint_as_float(min(__float_as_uint(x), 0xff7fffffu));
-}
-__device__ __forceinline__ float at_least_flt_min(float x_nonneg) {
-    return __uint_as_float(max(__float_as_uint(x_nonneg), 0x00800000u));
-}
+extern "C" __device__ float sqr_fmul_legacy(float, float) __asm("llvm.amdgcn.fmul.legacy");
+__device__ __forceinline__ float mul0(float zero_wins, float x) { return sqr_fmul_legacy(zero_wins, x); }
 
 template <int VP>
 __device__ __forceinline__ void pair_adjoint(cf_ptr r, const PairEval& ev, const float dd[3], float dfn, float da,
                                              float x[VP]) {
     const float a_ = r[12], b_ = r[13], e_ = r[14];
-    const float bia = ev.Bs * hw_rcp(at_least_flt_min(ev.A));
+    const float bia = mul0(ev.Bs, hw_rcp(ev.A));
     const float db = dfn * bia;
-    const float g0 = ev.u != 0.0f ? db * (ev.X * hw_rcp(ev.u)) : 0.0f;
-    const float g1 = ev.v != 0.0f ? db * (ev.Y * hw_rcp(ev.v)) : 0.0f;
-    const float g2 = ev.w != 0.0f ? dfn * (ev.Zs * hw_rcp(ev.w)) : 0.0f;
-    const float lA = finite_below(ev.lA), lu = finite_below(ev.lu);
-    const float lv = finite_below(ev.lv), lw = finite_below(ev.lw);
-    const float bla = ev.Bs * lA;
-    const float S = fmaf(ev.X, lu, ev.Y * lv);
+    const float g0 = db * mul0(ev.X, hw_rcp(ev.u));
+    const float g1 = db * mul0(ev.Y, hw_rcp(ev.v));
+    const float g2 = dfn * mul0(ev.Zs, hw_rcp(ev.w));
+    const float bla = mul0(ev.Bs, ev.lA);
+    const float S = mul0(ev.X, ev.lu) + mul0(ev.Y, ev.lv);
     x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
-    x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * (ev.Zs * lw)), x[A_E1]);
+    x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * mul0(ev.Zs, ev.lw)), x[A_E1]);
     x[A_E2] = fmaf(dfn, fmaf(-a_, bia * S, bla), x[A_E2]);
     x[A_XS + 0] += g0; x[A_XS + 1] += g1; x[A_XS + 2] += g2;
     x[A_R + 0] = fmaf(g0, dd[0], x[A_R + 0]);
