@@ -707,9 +707,9 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
 extern "C" __device__ float sqr_fmul_legacy(float, float) __asm("llvm.amdgcn.fmul.legacy");
 __device__ __forceinline__ float mul0(float zero_wins, float x) { return sqr_fmul_legacy(zero_wins, x); }
 
-template <int VP>
-__device__ __forceinline__ void pair_adjoint(cf_ptr r, const PairEval& ev, const float dd[3], float dfn, float da,
-                                             float x[VP]) {
+template <int VP, typename RecT>
+__device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, const float dd[3], float dfn,
+                                             float da, float x[VP]) {
     const float a_ = r[12], b_ = r[13], e_ = r[14];
     const float bia = mul0(ev.Bs, hw_rcp(ev.A));
     const float db = dfn * bia;
@@ -1016,11 +1016,12 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
             const float sig = r[15];
+            const RecRegs rr = pin_record(r);
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
                 if (mem[jj]) {
                     if (STATS) { st[1] += 1; if (pair_kept(r, sx[jj], sy[jj], sz[jj])) st[2] += 1; }
-                    const float p = eval_p(r, sx[jj], sy[jj], sz[jj]);
+                    const float p = eval_p(rr, sx[jj], sy[jj], sz[jj]);
                     if (p != 0.0f) {
                         a[jj] = fmaf(p, sig, a[jj]);
                         G[jj] = fmaf(p, gam, G[jj]);
@@ -1075,6 +1076,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
             const float sig = r[15];
+            const RecRegs rr = pin_record(r);
             float x[VP];
 #pragma unroll
             for (int i = 0; i < VP; ++i) x[i] = 0.0f;
@@ -1085,13 +1087,13 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 if (mem[jj]) {
                     PairEval ev;
                     float dd[3];
-                    const bool kept = eval_pair(r, sx[jj], sy[jj], sz[jj], dd, ev);
+                    const bool kept = eval_pair(rr, sx[jj], sy[jj], sz[jj], dd, ev);
                     if (STATS) { st[4] += 1; if (kept) st[5] += 1; }
                     if (kept && ev.p > 0.0f) {
                         contrib = true;
                         const float da = a[jj], w = G[jj];
                         const float dfn = ev.p * fmaf(da, sig, w * gam);
-                        pair_adjoint<VP>(r, ev, dd, dfn, da, x);
+                        pair_adjoint<VP>(rr, ev, dd, dfn, da, x);
                         om = fmaf(w, ev.p, om);
                     }
                 }

@@ -101,6 +101,25 @@ __device__ __forceinline__ int pinned_centre_axis(float m, float lo, float inv, 
     return (int)floorf(q);
 }
 
+// The first 17 record entries (everything the pair evaluation reads) held in
+// SGPRs for the whole walk over one primitive's samples.  The empty asm makes
+// each value opaque, so the compiler keeps it in its register instead of
+// re-issuing the scalar load (and waiting for it) at every use.
+struct RecRegs {
+    float v[17];
+    __device__ __forceinline__ float operator[](int i) const { return v[i]; }
+};
+__device__ __forceinline__ RecRegs pin_record(cf_ptr r) {
+    RecRegs o;
+#pragma unroll
+    for (int i = 0; i < 17; ++i) {
+        float x = r[i];
+        asm volatile("" : "+s"(x));
+        o.v[i] = x;
+    }
+    return o;
+}
+
 // ---------------------------------------------------------------------------
 // Pair evaluation p_o(x, S_k) = exp(-f(R(x - m)/s)) (Eq. eq:sq_occupancy_prob).
 // ---------------------------------------------------------------------------
@@ -120,7 +139,8 @@ constexpr float L2_LOG2E = 0.5287663729448977f;
 // the adjoint's per-primitive factors absorb the ln 2.  p may differ from
 // eval_p's in the last bit.  Returns false when the pair is culled (float32
 // exp(-f) would be exactly 0).
-__device__ __forceinline__ bool eval_pair(cf_ptr rec, float x, float y, float z,
+template <typename RecT>
+__device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, float z,
                                           float dxyz[3], PairEval& e) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
     dxyz[0] = dx; dxyz[1] = dy; dxyz[2] = dz;
@@ -154,7 +174,8 @@ __device__ __forceinline__ bool pair_kept(cf_ptr rec, float x, float y, float z)
 }
 
 // Forward-only evaluation: returns p (0 when culled).
-__device__ __forceinline__ float eval_p(cf_ptr rec, float x, float y, float z) {
+template <typename RecT>
+__device__ __forceinline__ float eval_p(const RecT& rec, float x, float y, float z) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
     const float u = fmaf(rec[3], dx, fmaf(rec[4], dy, rec[5] * dz));
     const float v = fmaf(rec[6], dx, fmaf(rec[7], dy, rec[8] * dz));
