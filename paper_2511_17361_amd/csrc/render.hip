@@ -408,13 +408,12 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
 #pragma unroll
             for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
             if (STATS && act) { ++st_samples; st_pairs += n; }
-            auto add_pair = [&](int k) {
-                const cf_ptr r = X.rec + (size_t)k * REC;
-                const float p = eval_p(r, cur.x, cur.y, cur.z);
-                if (STATS && pair_kept(r, cur.x, cur.y, cur.z)) ++st_nz;
+            // rr, lg: the record and logits of k, wave-uniform, in SGPRs
+            auto add_pair = [&](int k, const auto& rr, const Pinned<CP>& lg) {
+                const float p = eval_p(rr, cur.x, cur.y, cur.z);
+                if (STATS && pair_kept(X.rec + (size_t)k * REC, cur.x, cur.y, cur.z)) ++st_nz;
                 if (p != 0.0f) {
-                    a = fmaf(p, r[15], a);
-                    const cf_ptr lg = X.lgp + (size_t)k * CP;
+                    a = fmaf(p, rr[15], a);
 #pragma unroll
                     for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
                 }
@@ -428,7 +427,12 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 if (act) {
                     for (int e = 0; e < n0; ++e) {
                         const int k = X.ids[f0 + e];
-                        if ((unsigned)k < (unsigned)X.n) add_pair(k);
+                        if ((unsigned)k < (unsigned)X.n) {
+                            Pinned<17> rr;
+                            Pinned<CP> lg;
+                            pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+                            add_pair(k, rr, lg);
+                        }
                     }
                 }
             } else if (bm) {
@@ -448,11 +452,13 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 }
                 wave_lds_sync();
                 for_each_marked<true>(bm, nw, lane, [&](int k) {
-                    const cf_ptr r = X.rec + (size_t)k * REC;
-                    const bool mem = act && in_range(cur.ix, __float_as_int(r[20])) &&
-                                     in_range(cur.iy, __float_as_int(r[21])) &&
-                                     in_range(cur.iz, __float_as_int(r[22]));
-                    if (mem) add_pair(k);
+                    Pinned<23> rr;
+                    Pinned<CP> lg;
+                    pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+                    const bool mem = act & in_range(cur.ix, __float_as_int(rr[20])) &
+                                     in_range(cur.iy, __float_as_int(rr[21])) &
+                                     in_range(cur.iz, __float_as_int(rr[22]));
+                    if (mem) add_pair(k, rr, lg);
                 });
                 wave_lds_sync();
             } else {
@@ -468,7 +474,12 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                     if (mine) {
                         for (int e = 0; e < ng; ++e) {
                             const int k = X.ids[fg + e];
-                            if ((unsigned)k < (unsigned)X.n) add_pair(k);
+                            if ((unsigned)k < (unsigned)X.n) {
+                                Pinned<17> rr;
+                                Pinned<CP> lg;
+                                pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+                                add_pair(k, rr, lg);
+                            }
                         }
                     }
                     pend = pend && !mine;
@@ -1016,7 +1027,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
             const float sig = r[15];
-            const RecRegs rr = pin_record(r);
+            const Pinned<17> rr = pin<17>(r);
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
                 if (mem[jj]) {
@@ -1076,7 +1087,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
             const float sig = r[15];
-            const RecRegs rr = pin_record(r);
+            const Pinned<17> rr = pin<17>(r);
             float x[VP];
 #pragma unroll
             for (int i = 0; i < VP; ++i) x[i] = 0.0f;

@@ -101,23 +101,37 @@ __device__ __forceinline__ int pinned_centre_axis(float m, float lo, float inv, 
     return (int)floorf(q);
 }
 
-// The first 17 record entries (everything the pair evaluation reads) held in
-// SGPRs for the whole walk over one primitive's samples.  The empty asm makes
-// each value opaque, so the compiler keeps it in its register instead of
-// re-issuing the scalar load (and waiting for it) at every use.
-struct RecRegs {
-    float v[17];
+// N wave-uniform floats (a primitive's record, its logits) held in SGPRs for
+// as long as a walk uses them.  The empty asm makes each value opaque, so the
+// compiler keeps it in its register instead of re-issuing the scalar load
+// (and waiting for it) at every use, and the loads of one group are issued
+// together behind a single wait.  A record needs its first 17 entries for the
+// pair evaluation, 23 with the clipped box.
+template <int N>
+struct Pinned {
+    float v[N];
     __device__ __forceinline__ float operator[](int i) const { return v[i]; }
 };
-__device__ __forceinline__ RecRegs pin_record(cf_ptr r) {
-    RecRegs o;
+template <int N>
+__device__ __forceinline__ Pinned<N> pin(cf_ptr r) {
+    Pinned<N> o;
 #pragma unroll
-    for (int i = 0; i < 17; ++i) {
-        float x = r[i];
-        asm volatile("" : "+s"(x));
-        o.v[i] = x;
-    }
+    for (int i = 0; i < N; ++i) o.v[i] = r[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+s"(o.v[i]));
     return o;
+}
+// Two groups (a record and the logits) behind one wait.
+template <int N, int M>
+__device__ __forceinline__ void pin2(cf_ptr r, Pinned<N>& a, cf_ptr q, Pinned<M>& b) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) a.v[i] = r[i];
+#pragma unroll
+    for (int i = 0; i < M; ++i) b.v[i] = q[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+s"(a.v[i]));
+#pragma unroll
+    for (int i = 0; i < M; ++i) asm volatile("" : "+s"(b.v[i]));
 }
 
 // ---------------------------------------------------------------------------
