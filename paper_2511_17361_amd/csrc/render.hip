@@ -1016,18 +1016,19 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
         for_each_marked(bm, nw, lane, [&](int k) {
             const cf_ptr r = X.rec + (size_t)k * REC;
-            const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+            Pinned<23> rr;
+            Pinned<CP> lg;
+            pin2(r, rr, X.lgp + (size_t)k * CP, lg);
+            const int bx = __float_as_int(rr[20]), by = __float_as_int(rr[21]), bz = __float_as_int(rr[22]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            const cf_ptr lg = X.lgp + (size_t)k * CP;
             float gam = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
-            const float sig = r[15];
-            const Pinned<17> rr = pin<17>(r);
+            const float sig = rr[15];
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
                 if (mem[jj]) {
@@ -1076,18 +1077,19 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         // ---- pass 2: per-primitive adjoint over the union -------------------
         for_each_marked(bm, nw, lane, [&](int k) {
             const cf_ptr r = X.rec + (size_t)k * REC;
-            const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+            Pinned<23> rr;
+            Pinned<CP> lg;
+            pin2(r, rr, X.lgp + (size_t)k * CP, lg);
+            const int bx = __float_as_int(rr[20]), by = __float_as_int(rr[21]), bz = __float_as_int(rr[22]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            const cf_ptr lg = X.lgp + (size_t)k * CP;
             float gam = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
-            const float sig = r[15];
-            const Pinned<17> rr = pin<17>(r);
+            const float sig = rr[15];
             float x[VP];
 #pragma unroll
             for (int i = 0; i < VP; ++i) x[i] = 0.0f;
