@@ -941,8 +941,18 @@ __global__ __launch_bounds__(256) void k_render_bwd(Ctx P) {
 //     reductions and atomics shrink by the number of chunk samples that share
 //     a primitive.
 // ---------------------------------------------------------------------------
+// With C = 17 the logit gradients of a (chunk, primitive) are not put through
+// the 64-lane transposing reduction: each lane leaves om = sum_j w_j p_jk in LDS
+// and lane (q, c) sums om x g_S[c] over the 16 lanes of row q for class c < 16,
+// from a per-wave copy of g_S[0..15] in LDS written once per tile; the four
+// rows are then added with two lane swaps.  Only the 15 geometric sums and
+// class 16 go through the reduction (16 values instead of 32).
+constexpr int LGS_STRIDE = 68;                     // floats per class row (bank-spread, 16-byte aligned)
+constexpr int LGS_FLOATS = 16 * LGS_STRIDE + 64;   // g_S rows + the om row
+template <int CP> struct SplitLogits { static constexpr bool on = CP == 17; };
+
 template <int CP, int KC, bool STATS>
-__device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint32_t* bm) {
+__device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint32_t* bm, float* lgs) {
     const SceneDev& S = P.desc->s[s];
     const RayLane rl = setup_lane(P, S, tile);
     const SceneIndex X = scene_index<CP>(P, s, S);
@@ -964,6 +974,11 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
     const int64_t gbase = S.ray_off * P.C + (int64_t)rl.cam * P.C * HW + lane_pix(rl, S);
 #pragma unroll
     for (int c = 0; c < CP; ++c) gS[c] = (rl.valid && P.g_sem && c < P.C) ? P.g_sem[gbase + c * HW] : 0.0f;
+    constexpr bool SPLIT = SplitLogits<CP>::on;
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) lgs[c * LGS_STRIDE + lane] = gS[c];
+    }
 
     int64_t st[6] = {0, 0, 0, 0, 0, 0};
     float Q = 0.0f;
@@ -1090,9 +1105,10 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
             const float sig = rr[15];
-            float x[VP];
+            constexpr int VR = SPLIT ? 16 : VP;     // values reduced across the wave
+            float x[VR];
 #pragma unroll
-            for (int i = 0; i < VP; ++i) x[i] = 0.0f;
+            for (int i = 0; i < VR; ++i) x[i] = 0.0f;
             float om = 0.0f;          // sum_j w_j p_jk
             bool contrib = false;
 #pragma unroll
@@ -1106,19 +1122,45 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                         contrib = true;
                         const float da = a[jj], w = G[jj];
                         const float dfn = ev.p * fmaf(da, sig, w * gam);
-                        pair_adjoint<VP>(rr, ev, dd, dfn, da, x);
+                        pair_adjoint<VR>(rr, ev, dd, dfn, da, x);
                         om = fmaf(w, ev.p, om);
                     }
                 }
             }
             if (wave_ballot(contrib) == 0) return;
+            if constexpr (SPLIT) {
+                // classes 0..15: lane (q, c) = (lane / 16, lane % 16)
+                float* omr = lgs + 16 * LGS_STRIDE;
+                omr[lane] = om;
+                wave_lds_sync();
+                const int q = lane >> 4, c = lane & 15;
+                const float4* o4 = reinterpret_cast<const float4*>(omr + 16 * q);
+                const float4* g4 = reinterpret_cast<const float4*>(lgs + c * LGS_STRIDE + 16 * q);
+                float part = 0.0f;
+#pragma unroll 1
+                for (int i = 0; i < 4; ++i) {
+                    const float4 o = o4[i], g = g4[i];
+                    part = fmaf(o.x, g.x, part);
+                    part = fmaf(o.y, g.y, part);
+                    part = fmaf(o.z, g.z, part);
+                    part = fmaf(o.w, g.w, part);
+                }
+                wave_lds_sync();
+                const float lgt = row_sum4(part);
+                x[15] = om * gS[16];
+                const float tot = transpose_reduce<16>(x, lane);
+                const int vi = lane >> 2;              // value index held by this lane
+                if ((lane & 3) == 0) atomicAdd(acc + (size_t)k * VP + (vi < 15 ? vi : A_LG + 16), tot);
+                if (lane < 16) atomicAdd(acc + (size_t)k * VP + A_LG + lane, lgt);
+            } else {
 #pragma unroll
-            for (int c = 0; c < CP; ++c) x[A_LG + c] = om * gS[c];
-            const float tot = transpose_reduce<VP>(x, lane);
-            constexpr int shift = 6 - Log2<VP>::v;
-            const int vi = lane >> shift;
-            if (((lane & ((1 << shift) - 1)) == 0) && vi < V && (vi < A_LG || vi - A_LG < P.C))
-                atomicAdd(acc + (size_t)k * VP + vi, tot);
+                for (int c = 0; c < CP; ++c) x[A_LG + c] = om * gS[c];
+                const float tot = transpose_reduce<VP>(x, lane);
+                constexpr int shift = 6 - Log2<VP>::v;
+                const int vi = lane >> shift;
+                if (((lane & ((1 << shift) - 1)) == 0) && vi < V && (vi < A_LG || vi - A_LG < P.C))
+                    atomicAdd(acc + (size_t)k * VP + vi, tot);
+            }
         });
     }
     if (STATS && rl.valid)
@@ -1129,10 +1171,14 @@ template <int CP, int KC, bool STATS, bool PERSIST>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP, KC), 8))) void k_render_bwd_km(
     Ctx P) {
     extern __shared__ uint32_t bm_all[];
-    uint32_t* bm = bm_all + (size_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * P.bitmap_words;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* bm = bm_all + (size_t)wave * P.bitmap_words;
+    // per-wave logit scratch after the block's bitmaps (C = 17 only)
+    float* lgs = reinterpret_cast<float*>(bm_all + (size_t)(blockDim.x >> 6) * P.bitmap_words) +
+                 (size_t)wave * LGS_FLOATS;
     for_each_tile<PERSIST>(P, [&](int t, const Ctx& Q) {
         const int s = find_scene(Q.desc, t);
-        bwd_km_tile<CP, KC, STATS>(Q, s, t - Q.desc->s[s].tile_off, bm);
+        bwd_km_tile<CP, KC, STATS>(Q, s, t - Q.desc->s[s].tile_off, bm, lgs);
     });
 }
 
@@ -1618,6 +1664,11 @@ static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, co
 static bool bitmap_fits(int max_n, int wpb) {
     return (size_t)wpb * bitmap_words(max_n) * sizeof(uint32_t) <= 64 * 1024;
 }
+// LDS of a primitive-major backward block: the bitmaps, then (C = 17) each
+// wave's logit scratch.
+static size_t km_lds_bytes(int words, int wpb, int CP) {
+    return (size_t)wpb * ((size_t)words * sizeof(uint32_t) + (CP == 17 ? LGS_FLOATS * sizeof(float) : 0));
+}
 
 template <int CP, bool LOSS>
 static void fwd_launch(const Ctx& P, const TuneDev& t, size_t shm, hipStream_t st) {
@@ -1816,13 +1867,14 @@ hipError_t launch_batch_bwd_sq_major(const GridDev& g, const BatchDesc& d, const
 bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb) {
     if (!(K == 4 || K == 8)) return false;
     if (g.X > KM_MAX_XY || g.Y > KM_MAX_XY || g.Z > KM_MAX_Z) return false;
-    return bitmap_fits(max_n, wpb);
+    // sized for the largest per-wave scratch (C = 17), whatever C is
+    return km_lds_bytes(bitmap_words(max_n), wpb, 17) <= 64 * 1024;
 }
 
 template <int CP, int KC>
 static void bwd_km_launch(const Ctx& P, const TuneDev& t, hipStream_t st) {
     const int wpb = t.waves_per_block;
-    const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);
+    const size_t shm = km_lds_bytes(P.bitmap_words, wpb, CP);
     if (P.stats) {
         launch_tiles(k_render_bwd_km<CP, KC, true, false>, false, P, wpb, shm, st);
     } else if (t.persistent) {

@@ -244,15 +244,16 @@ constexpr int DPP_ROW_HALF_MIRROR = 0x141;
 constexpr int DPP_QUAD_SWAP2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int DPP_QUAD_SWAP1 = 0xB1;   // quad_perm [1,0,3,2]
 
-// Sum VP (32 or 64) values over the 64 lanes of a wavefront with a
+// Sum VP (16, 32 or 64) values over the 64 lanes of a wavefront with a
 // transposing butterfly: at each level a lane keeps half of its values and
 // adds its partner's partial sums of that half.  Levels use
 // v_permlane32_swap, v_permlane16_swap, DPP row_mirror, row_half_mirror and
-// two quad permutes, so no LDS is touched.  On return lane l holds the total
-// of value index l >> (6 - log2 VP).  All 64 lanes must be active.
+// two quad permutes, so no LDS is touched; once one value is left, the
+// remaining levels are plain sums over the quad.  On return lane l holds the
+// total of value index l >> (6 - log2 VP).  All 64 lanes must be active.
 template <int VP>
 __device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
-    static_assert(VP == 32 || VP == 64, "VP must be 32 or 64");
+    static_assert(VP == 16 || VP == 32 || VP == 64, "VP must be 16, 32 or 64");
     constexpr int h1 = VP / 2, h2 = h1 / 2, h3 = h2 / 2, h4 = h3 / 2, h5 = h4 / 2;
 #pragma unroll
     for (int i = 0; i < h1; ++i) {
@@ -279,19 +280,33 @@ __device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
         const float hi = x[h4 + i] + dpp_f<DPP_ROW_HALF_MIRROR>(x[h4 + i]);
         x[i] = b2 ? hi : lo;
     }
-#pragma unroll
-    for (int i = 0; i < h5; ++i) {
-        const float lo = x[i] + dpp_f<DPP_QUAD_SWAP2>(x[i]);
-        const float hi = x[h5 + i] + dpp_f<DPP_QUAD_SWAP2>(x[h5 + i]);
-        x[i] = b1 ? hi : lo;
-    }
-    if constexpr (VP == 64) {
-        const float lo = x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
-        const float hi = x[1] + dpp_f<DPP_QUAD_SWAP1>(x[1]);
-        return b0 ? hi : lo;
+    if constexpr (VP == 16) {
+        const float t = x[0] + dpp_f<DPP_QUAD_SWAP2>(x[0]);
+        return t + dpp_f<DPP_QUAD_SWAP1>(t);
     } else {
-        return x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
+#pragma unroll
+        for (int i = 0; i < h5; ++i) {
+            const float lo = x[i] + dpp_f<DPP_QUAD_SWAP2>(x[i]);
+            const float hi = x[h5 + i] + dpp_f<DPP_QUAD_SWAP2>(x[h5 + i]);
+            x[i] = b1 ? hi : lo;
+        }
+        if constexpr (VP == 64) {
+            const float lo = x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
+            const float hi = x[1] + dpp_f<DPP_QUAD_SWAP1>(x[1]);
+            return b0 ? hi : lo;
+        } else {
+            return x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
+        }
     }
+}
+
+// Sum of v over the four 16-lane rows: every lane gets the total of its
+// position in the row (v_permlane32_swap, v_permlane16_swap).
+__device__ __forceinline__ float row_sum4(float v) {
+    const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane16_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
