@@ -1137,14 +1137,17 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 const float4* o4 = reinterpret_cast<const float4*>(omr + 16 * q);
                 const float4* g4 = reinterpret_cast<const float4*>(lgs + c * LGS_STRIDE + 16 * q);
                 float part = 0.0f;
-#pragma unroll 1
+#pragma unroll
                 for (int i = 0; i < 4; ++i) {
+                    // one pair of 16-byte reads at a time (immediate offsets, 8 registers)
+                    __builtin_amdgcn_sched_barrier(0);
                     const float4 o = o4[i], g = g4[i];
                     part = fmaf(o.x, g.x, part);
                     part = fmaf(o.y, g.y, part);
                     part = fmaf(o.z, g.z, part);
                     part = fmaf(o.w, g.w, part);
                 }
+                __builtin_amdgcn_sched_barrier(0);
                 wave_lds_sync();
                 const float lgt = row_sum4(part);
                 x[15] = om * gS[16];
