@@ -49,6 +49,11 @@ R9  Depth is range along the unit ray, no normalisation by sum(w); an empty
     ray renders depth 0, semantics 0, transmittance 1.
 R10 "Class probabilities" = softmax over classes of the rendered semantic
     vector S_hat (max-subtracted).
+R21 Influence threshold of the index (the Supplement's future work on
+    occupancy-aware indexing): with theta > 0 a primitive is listed only in
+    the voxels of its N_v cube that meet the world box of
+    max(|u|,|v|,|w|) <= ln(sigma/theta)^(eps1/2), a box that holds every point
+    where p_o sigma >= theta (see influence_boxes).
 """
 from __future__ import annotations
 
@@ -57,7 +62,7 @@ import math
 import numpy as np
 
 __all__ = [
-    "pinned_inv_voxel", "sample_depths", "voxel_of_points", "centre_boxes",
+    "pinned_inv_voxel", "sample_depths", "voxel_of_points", "centre_boxes", "influence_boxes",
     "build_index", "rotation_matrix", "inside_outside", "occupancy",
     "render", "render_grad", "box_volume_total",
 ]
@@ -119,6 +124,58 @@ def centre_boxes(means: np.ndarray, grid):
     return blo, bhi
 
 
+def influence_boxes(prims, grid):
+    """List region of each primitive under an influence threshold theta
+    (reading R21; Supplement "Limitations and Future Work": keep a primitive
+    out of the voxels where its occupancy times opacity stays below theta).
+
+    f >= max(|u|,|v|,|w|)^(2/eps1), so p_o sigma >= theta implies
+    max(|u|,|v|,|w|) <= r = ln(sigma/theta)^(eps1/2).  The world-space box of
+    that canonical cube, x - m = R^T diag(s) u, has half-extent
+    h_a = r (|R_0a| s_0 + |R_1a| s_1 + |R_2a| s_2).  The region is the N_v cube
+    of R4 intersected with floor(((m_a -/+ h_a) - lo_a) / voxel) per axis, all
+    in FP64 on the FP32 inputs; it is empty where sigma <= theta.  theta = 0
+    (the default) is the N_v cube itself.  Returns (lo[N,3], hi[N,3]) int64."""
+    blo, bhi = centre_boxes(prims.means, grid)
+    theta = float(getattr(grid, "theta", 0.0))
+    if not theta > 0.0:
+        return blo, bhi
+    q = np.asarray(prims.quats, np.float64)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    nrm = np.sqrt(w * w + x * x + y * y + z * z)
+    w, x, y, z = w / nrm, x / nrm, y / nrm, z / nrm
+    R = np.empty((q.shape[0], 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - w * z)
+    R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y)
+    R[:, 2, 1] = 2 * (y * z + w * x)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    s = np.asarray(prims.scales, np.float64)
+    e1 = np.asarray(prims.eps, np.float64)[:, 0]
+    sig = np.asarray(prims.opacity, np.float64)
+    live = sig > theta
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(live, np.exp(0.5 * e1 * np.log(np.log(np.where(live, sig, 1.0) / theta))), 0.0)
+    h = r[:, None] * (np.abs(R[:, 0, :]) * s[:, 0:1] + np.abs(R[:, 1, :]) * s[:, 1:2] + np.abs(R[:, 2, :]) * s[:, 2:3])
+    m = np.asarray(prims.means, np.float64)
+    lo = np.asarray(grid.lo, F32).astype(np.float64)
+    vs = float(F32(grid.voxel))
+    slo = np.floor(((m - h) - lo) / vs)
+    shi = np.floor(((m + h) - lo) / vs)
+    big = float(max(int(np.max(grid.dims)) + int(grid.nv) + 2, 4))
+    slo = np.clip(np.nan_to_num(slo, nan=big), -big, big).astype(np.int64)
+    shi = np.clip(np.nan_to_num(shi, nan=-big), -big, big).astype(np.int64)
+    tlo = np.maximum(blo, slo)
+    thi = np.minimum(bhi, shi)
+    thi[~live] = -1
+    tlo[~live] = 0
+    return tlo, thi
+
+
 def box_volume_total(means, grid) -> int:
     """sum_k |box_k| (the number of index entries E)."""
     blo, bhi = centre_boxes(means, grid)
@@ -126,18 +183,26 @@ def box_volume_total(means, grid) -> int:
     return int(np.prod(ext, axis=1).sum())
 
 
-def build_index(means: np.ndarray, grid):
+def build_index(prims, grid):
     """V_n, V_f, V_sq ("Preliminary Construction").
 
-    Every primitive emits the (voxel, id) pairs of its clipped box; the pairs
-    are ordered by (voxel, id); V_n counts pairs per voxel and V_f is the
-    exclusive prefix sum of V_n.  Returns (counts, offsets, ids) as int32 and
-    the total E."""
+    Every primitive emits the (voxel, id) pairs of its clipped box (R4, and
+    R21 when the grid carries an influence threshold theta > 0); the pairs are
+    ordered by (voxel, id); V_n counts pairs per voxel and V_f is the exclusive
+    prefix sum of V_n.  `prims` is a Prims, or just the [N,3] centres when
+    theta = 0.  Returns (counts, offsets, ids) as int32 and the total E."""
     dims = tuple(int(d) for d in grid.dims)
     nvox = dims[0] * dims[1] * dims[2]
-    blo, bhi = centre_boxes(means, grid)
+    if hasattr(prims, "means"):
+        blo, bhi = influence_boxes(prims, grid)
+        n = prims.n
+    else:
+        if float(getattr(grid, "theta", 0.0)) > 0.0:
+            raise ValueError("an influence threshold needs the primitives, not only their centres")
+        blo, bhi = centre_boxes(prims, grid)
+        n = prims.shape[0]
     vox_parts, id_parts = [], []
-    for k in range(means.shape[0]):
+    for k in range(n):
         if np.any(blo[k] > bhi[k]):
             continue
         ix = np.arange(blo[k, 0], bhi[k, 0] + 1)
@@ -326,7 +391,7 @@ def render(grid, prims, rays, march, index=None, brute=False, ray_ids=None, batc
     sem/probs [cams,C,H,W].  With `ray_ids` (flat ray indices) only those rays
     are rendered and the outputs are flat: depth [n], sem [n,C]."""
     if index is None and not brute:
-        index = build_index(prims.means, grid)[:3]
+        index = build_index(prims, grid)[:3]
     P = _Prep(prims)
     o = rays.origins.reshape(-1, 3)
     d = rays.dirs.reshape(-1, 3)
@@ -431,7 +496,7 @@ def render_grad(grid, prims, rays, march, g_depth, g_sem, index=None, brute=Fals
     runs back to front: Q_L = 0, Q_j = alpha_j G_j + (1 - alpha_j) Q_{j+1},
     dL/dalpha_j = T_j (G_j - Q_{j+1}), G_j = g_D t_j + <g_S, s_j>."""
     if index is None and not brute:
-        index = build_index(prims.means, grid)[:3]
+        index = build_index(prims, grid)[:3]
     P = _Prep(prims)
     N, C = prims.logits.shape
     o = rays.origins.reshape(-1, 3)

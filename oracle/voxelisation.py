@@ -69,7 +69,7 @@ def voxelise(grid, prims, index=None, brute=False, tau=0.05, voxel_ids=None, chu
         inside = np.all((vi[:, None, :] >= blo[None]) & (vi[:, None, :] <= bhi[None]), axis=2)
         pv, pk = np.nonzero(inside)                  # pairs (voxel row, primitive), ascending k per voxel
     else:
-        counts, offsets, ids = (build_index(prims.means, grid)[:3] if index is None else index[:3])
+        counts, offsets, ids = (build_index(prims, grid)[:3] if index is None else index[:3])
         n = counts[vids].astype(np.int64)
         pv = np.repeat(np.arange(vids.size), n)
         start = np.repeat(offsets[vids].astype(np.int64), n)

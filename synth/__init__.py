@@ -28,6 +28,7 @@ class Grid:
     voxel: float
     dims: tuple
     nv: int = 5  # neighbourhood half-width N_v (Sec. "Implementation Details")
+    theta: float = 0.0  # influence threshold of the index (0: the N_v cube)
 
     @property
     def n_voxels(self) -> int:
