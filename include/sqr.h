@@ -48,12 +48,24 @@ typedef int32_t sq_status;
  * (half-open; the upper face is outside).  The linear voxel id used by the
  * index ("hashing" of the paper) is v = (ix*dims[1] + iy)*dims[2] + iz.
  * nv is the neighbourhood half-width N_v: primitive k is listed in every voxel
- * v with max_axis |v - c_k| <= nv, where c_k is the voxel containing m_k. */
+ * v with max_axis |v - c_k| <= nv, where c_k is the voxel containing m_k.
+ *
+ * theta is the index's influence threshold (the occupancy-aware indexing of
+ * the Supplement's "Limitations and Future Work"), in [0, 1).  0 gives the
+ * paper's index above.  With theta > 0 primitive k is listed only in the
+ * voxels of its N_v cube that meet the world-space box of
+ * max(|u|,|v|,|w|) <= ln(sigma_k/theta)^(eps1_k/2), evaluated in FP64: that
+ * box holds every point where p_o * sigma_k >= theta, since
+ * f >= max(|u|,|v|,|w|)^(2/eps1).  A primitive with sigma_k <= theta is listed
+ * nowhere.  The render then drops exactly the (sample, primitive) pairs whose
+ * voxel lies outside that box, each with p_o * sigma_k < theta.  Every call
+ * that takes the grid (index, renders, voxelisation) uses the same lists. */
 typedef struct {
     float   lo[3];
     float   voxel;
     int32_t dims[3];
     int32_t nv;
+    float   theta;
 } sq_grid;
 
 /* Superquadric -> voxel CSR lists: the paper's V_n (counts), V_f (offsets,

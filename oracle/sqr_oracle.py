@@ -137,7 +137,7 @@ def influence_boxes(prims, grid):
     in FP64 on the FP32 inputs; it is empty where sigma <= theta.  theta = 0
     (the default) is the N_v cube itself.  Returns (lo[N,3], hi[N,3]) int64."""
     blo, bhi = centre_boxes(prims.means, grid)
-    theta = float(getattr(grid, "theta", 0.0))
+    theta = float(F32(getattr(grid, "theta", 0.0)))     # an FP32 parameter, as the kernels see it
     if not theta > 0.0:
         return blo, bhi
     q = np.asarray(prims.quats, np.float64)
@@ -336,7 +336,7 @@ def _march(grid, prims, rays_o, rays_d, march, index, brute, P, want_pairs):
     B = rays_o.shape[0]
     C = prims.logits.shape[1]
     counts, offsets, ids = index if index is not None else (None, None, None)
-    box_lo, box_hi = centre_boxes(prims.means, grid) if brute else (None, None)
+    box_lo, box_hi = influence_boxes(prims, grid) if brute else (None, None)
     t32 = sample_depths(march.n_samples, march.t_near, march.t_far)
     kappa = float(getattr(march, "kappa", 0.0))
     T = np.ones(B)

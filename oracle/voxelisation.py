@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .sqr_oracle import F32, _eval_pairs, _Prep, build_index, centre_boxes
+from .sqr_oracle import F32, _eval_pairs, _Prep, build_index, centre_boxes, influence_boxes
 
 __all__ = ["voxel_centres", "voxelise", "labels_from"]
 
@@ -64,7 +64,7 @@ def voxelise(grid, prims, index=None, brute=False, tau=0.05, voxel_ids=None, chu
     centre = np.stack([cx[ix], cy[iy], cz[iz]], axis=1).astype(np.float64)
 
     if brute:
-        blo, bhi = centre_boxes(prims.means, grid)
+        blo, bhi = influence_boxes(prims, grid)
         vi = np.stack([ix, iy, iz], axis=1)
         inside = np.all((vi[:, None, :] >= blo[None]) & (vi[:, None, :] <= bhi[None]), axis=2)
         pv, pk = np.nonzero(inside)                  # pairs (voxel row, primitive), ascending k per voxel

@@ -31,7 +31,8 @@ EXPORTED = [
 
 
 class SqGrid(ct.Structure):
-    _fields_ = [("lo", ct.c_float * 3), ("voxel", ct.c_float), ("dims", ct.c_int32 * 3), ("nv", ct.c_int32)]
+    _fields_ = [("lo", ct.c_float * 3), ("voxel", ct.c_float), ("dims", ct.c_int32 * 3), ("nv", ct.c_int32),
+                ("theta", ct.c_float)]
 
 
 class SqIndex(ct.Structure):

@@ -38,6 +38,7 @@ class Grid:
     voxel: float
     dims: tuple
     nv: int
+    theta: float = 0.0      # influence threshold of the index (0: the N_v cube)
 
     def c(self) -> L.SqGrid:
         g = L.SqGrid()
@@ -46,6 +47,7 @@ class Grid:
             g.dims[i] = int(self.dims[i])
         g.voxel = float(self.voxel)
         g.nv = int(self.nv)
+        g.theta = float(self.theta)
         return g
 
     @property
@@ -54,7 +56,8 @@ class Grid:
 
     @staticmethod
     def of(obj) -> "Grid":
-        return obj if isinstance(obj, Grid) else Grid(tuple(obj.lo), float(obj.voxel), tuple(obj.dims), int(obj.nv))
+        return obj if isinstance(obj, Grid) else Grid(tuple(obj.lo), float(obj.voxel), tuple(obj.dims), int(obj.nv),
+                                                      float(getattr(obj, "theta", 0.0)))
 
 
 @dataclass

@@ -39,11 +39,13 @@ bool grid_ok(const sq_grid* g) {
     if (!g) return false;
     for (int i = 0; i < 3; ++i)
         if (!(g->dims[i] > 0 && g->dims[i] <= 32767) || !std::isfinite(g->lo[i])) return false;
-    return std::isfinite(g->voxel) && g->voxel > 0.0f && g->nv >= 0 && g->nv <= 32767;
+    return std::isfinite(g->voxel) && g->voxel > 0.0f && g->nv >= 0 && g->nv <= 32767 && g->theta >= 0.0f &&
+           g->theta < 1.0f;
 }
 
 sq_status check_grid(const sq_grid* g) {
-    if (!grid_ok(g)) return fail(SQ_ERR_INVALID, "invalid grid (dims in [1,32767], voxel > 0, nv >= 0)");
+    if (!grid_ok(g))
+        return fail(SQ_ERR_INVALID, "invalid grid (dims in [1,32767], voxel > 0, nv >= 0, theta in [0, 1))");
     if ((int64_t)g->dims[0] * g->dims[1] * g->dims[2] >= ((int64_t)1 << 31))
         return fail(SQ_ERR_INVALID, "grid has >= 2^31 voxels");
     return SQ_OK;
@@ -56,6 +58,7 @@ sqr::GridDev to_dev(const sq_grid* g) {
     d.X = g->dims[0]; d.Y = g->dims[1]; d.Z = g->dims[2];
     d.nv = g->nv;
     d.vs = g->voxel;
+    d.theta = g->theta;
     return d;
 }
 
@@ -203,6 +206,9 @@ sq_status index_checked(const Plan& p, const sq_batch_io* io, void* ws, size_t w
     sq_status s;
     if ((s = check_io_index(p, io))) return s;
     if (!io->totals) return fail(SQ_ERR_INVALID, "index totals is NULL");
+    // the influence-thresholded boxes read every primitive parameter but the logits
+    if (p.g.theta > 0.0f && p.d.total_prims > 0 && (!io->quats || !io->scales || !io->eps || !io->opacity))
+        return fail(SQ_ERR_INVALID, "theta > 0 needs quats, scales, eps and opacity for the index");
     if ((s = check_ws(ws, ws_bytes, sqr::index_workspace_bytes(p.g, p.d)))) return s;
     return hip_status(sqr::launch_batch_index(p.g, p.d, to_dev(io), ws, stream), "build_index");
 }
@@ -353,7 +359,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 204; }
+int32_t sq_version(void) { return 205; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 

@@ -23,12 +23,14 @@ namespace sqr {
 constexpr int TILE_THREADS = 256;
 constexpr int CAND_CAP = 2048;      // LDS candidate batch (id + packed box = 16 B each)
 
-__global__ __launch_bounds__(256) void k_prep_boxes(const float* __restrict__ means, int n, GridDev g,
+__global__ __launch_bounds__(256) void k_prep_boxes(const float* __restrict__ means, const float* __restrict__ quats,
+                                                    const float* __restrict__ scales, const float* __restrict__ eps,
+                                                    const float* __restrict__ opacity, int n, GridDev g,
                                                     int4* __restrict__ boxes) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int b[3];
-    prim_box(g, means[3 * k], means[3 * k + 1], means[3 * k + 2], b);
+    prim_box(g, means + 3 * k, quats + 4 * k, scales + 3 * k, eps + 2 * k, opacity + k, b);
     boxes[k] = make_int4(b[0], b[1], b[2], 0);
 }
 
@@ -232,8 +234,8 @@ void launch_index_kernels(const GridDev& g, const BatchDesc& d, const BatchDesc*
     const int np = scan_parts(g);
     const int S = d.n_scenes;
     if (d.total_prims > 0)
-        hipLaunchKernelGGL(k_prep_boxes, dim3((d.total_prims + 255) / 256), dim3(256), 0, st, io.means,
-                           d.total_prims, g, boxes);
+        hipLaunchKernelGGL(k_prep_boxes, dim3((d.total_prims + 255) / 256), dim3(256), 0, st, io.means, io.quats,
+                           io.scales, io.eps, io.opacity, d.total_prims, g, boxes);
     const TileShape ts = pick_tile(g);
     const int ntiles = ts.ntx * ts.nty * ts.ntz;
     hipLaunchKernelGGL(k_tile_lists<false>, dim3(ntiles, S), dim3(TILE_THREADS), 0, st, desc_dev,

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const 
     r[16] = exp2f(0.5f * e1 * log2f(F_CULL));
     r[17] = is[0]; r[18] = is[1]; r[19] = is[2];
     int box[3];
-    prim_box(g, r[0], r[1], r[2], box);
+    prim_box(g, means + 3 * k, quats + 4 * k, scales + 3 * k, eps + 2 * k, opacity + k, box);
     r[20] = __int_as_float(box[0]); r[21] = __int_as_float(box[1]); r[22] = __int_as_float(box[2]);
     r[23] = 0.0f;
     for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < C ? logits[(size_t)k * C + c] : 0.0f;

@@ -54,6 +54,7 @@ struct GridDev {
     int X, Y, Z;
     int nv;
     float vs;           // voxel edge length
+    float theta;        // influence threshold of the index (0: the N_v cube)
 };
 
 struct SamplePos {
@@ -321,18 +322,62 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // Clipped box of a primitive, packed lo | hi << 16 per axis.  An empty box is
 // stored as lo = hi = 0x7fff on every axis: no voxel index reaches 0x7fff
 // (dims <= 32767), so every containment / overlap test fails.
-__device__ __forceinline__ void prim_box(const GridDev& g, float mx, float my, float mz, int out[3]) {
+//
+// With an influence threshold theta > 0 the N_v cube is further clipped to the
+// voxels meeting the world box of max(|u|,|v|,|w|) <= r = ln(sigma/theta)^(eps1/2)
+// (x - m = R^T diag(s) u, so its half-extent along axis a is
+// r (|R_0a| s_0 + |R_1a| s_1 + |R_2a| s_2)); empty where sigma <= theta.  That
+// part runs in FP64 with a fixed operation order and no contraction, so the
+// index build and the render's record preparation, which both call this
+// function on the same inputs, get the same box.
+__device__ __forceinline__ int clamp_cell(double c, int big) {
+    if (!(c >= -(double)big)) return -big;      // also NaN
+    if (c > (double)big) return big;
+    return (int)c;
+}
+// q, s, eps, sigma point at the primitive's quaternion, scales, (eps1, eps2)
+// and opacity; they are read only when theta > 0.
+__device__ __forceinline__ void prim_box(const GridDev& g, const float* m, const float* q, const float* s,
+                                         const float* eps, const float* sigma, int out[3]) {
     const int dims[3] = {g.X, g.Y, g.Z};
     const float lo[3] = {g.lox, g.loy, g.loz};
-    const float m[3] = {mx, my, mz};
     const float bound = (float)(max(max(g.X, g.Y), g.Z) + g.nv + 2);
+    int blo[3], bhi[3];
     bool empty = false;
     for (int ax = 0; ax < 3; ++ax) {
         const int c = pinned_centre_axis(m[ax], lo[ax], g.inv, bound);
-        const int blo = max(c - g.nv, 0);
-        const int bhi = min(c + g.nv, dims[ax] - 1);
-        if (blo > bhi) empty = true;
-        out[ax] = (blo & 0xffff) | (bhi << 16);
+        blo[ax] = max(c - g.nv, 0);
+        bhi[ax] = min(c + g.nv, dims[ax] - 1);
+    }
+    if (g.theta > 0.0f) {
+#pragma clang fp contract(off)
+        const double th = (double)g.theta, sg = (double)sigma[0];
+        if (!(sg > th)) {
+            empty = true;
+        } else {
+            double w = q[0], x = q[1], y = q[2], z = q[3];
+            const double nrm = sqrt(w * w + x * x + y * y + z * z);
+            w = w / nrm; x = x / nrm; y = y / nrm; z = z / nrm;
+            const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                                 2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                                 2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+            const double r = exp(0.5 * (double)eps[0] * log(log(sg / th)));
+            const double vs = (double)g.vs;
+            const int big = max(max(g.X, g.Y), g.Z) + g.nv + 2;
+            for (int ax = 0; ax < 3; ++ax) {
+                const double h = r * (fabs(R[ax]) * (double)s[0] + fabs(R[3 + ax]) * (double)s[1] +
+                                      fabs(R[6 + ax]) * (double)s[2]);
+                const double mm = (double)m[ax], l = (double)lo[ax];
+                const int slo = clamp_cell(floor(((mm - h) - l) / vs), big);
+                const int shi = clamp_cell(floor(((mm + h) - l) / vs), big);
+                blo[ax] = max(blo[ax], slo);
+                bhi[ax] = min(bhi[ax], shi);
+            }
+        }
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+        if (blo[ax] > bhi[ax]) empty = true;
+        out[ax] = (blo[ax] & 0xffff) | (bhi[ax] << 16);
     }
     if (empty) out[0] = out[1] = out[2] = EMPTY_BOX;
 }

@@ -150,6 +150,28 @@ def test_build_index_rejects_bad_arguments():
     assert rc == L.SQ_ERR_INVALID
 
 
+@pytest.mark.parametrize("theta", [-1e-3, 1.0, 2.5, float("nan"), float("inf")])
+def test_grid_rejects_bad_influence_threshold(theta):
+    lib = L.load()
+    g, p, i = _grid(), _prims(), _index()
+    g.theta = theta
+    rc = lib.sq_build_index(ct.byref(g), ct.byref(p), ct.byref(i), 0x100000, 1 << 30, None)
+    assert rc == L.SQ_ERR_INVALID and "theta" in lib.sq_last_error().decode()
+
+
+def test_thresholded_index_needs_the_primitive_parameters():
+    """With theta = 0 the index needs only the centres; with theta > 0 it
+    reads the quaternions, scales, eps and opacity as well."""
+    lib = L.load()
+    g, i = _grid(), _index()
+    g.theta = 1e-3
+    for f in ("quats", "scales", "eps", "opacity"):
+        p = _prims()
+        setattr(p, f, None)
+        rc = lib.sq_build_index(ct.byref(g), ct.byref(p), ct.byref(i), 0x100000, 1 << 30, None)
+        assert rc == L.SQ_ERR_INVALID and "theta" in lib.sq_last_error().decode(), f
+
+
 @pytest.mark.parametrize("mutate,code", [
     (lambda a: a.__setitem__("tau", float("nan")), L.SQ_ERR_INVALID),
     (lambda a: a.__setitem__("tau", float("inf")), L.SQ_ERR_INVALID),

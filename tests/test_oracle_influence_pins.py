@@ -148,3 +148,17 @@ def test_render_differs_by_less_than_theta_per_dropped_pair():
         worst = max(worst, float(np.max(da)))
         assert np.all(da <= dropped_max * theta * 1.001)
     assert worst > 0.0
+
+
+def test_brute_membership_equals_the_lists_with_theta():
+    """The renders from the thresholded lists and from the thresholded boxes
+    used as a membership predicate (brute) agree bit for bit."""
+    sc = _scene(5, n=30)
+    g = _with_theta(sc.grid, 1e-3)
+    a = oracle.render(g, sc.prims, sc.rays, sc.march)
+    b = oracle.render(g, sc.prims, sc.rays, sc.march, brute=True)
+    for k in ("depth", "sem", "t_final"):
+        assert np.array_equal(a[k], b[k]), k
+    va = oracle.voxelise(g, sc.prims)["density"]
+    vb = oracle.voxelise(g, sc.prims, brute=True)["density"]
+    assert np.array_equal(va, vb)
