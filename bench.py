@@ -182,9 +182,11 @@ def main():
     dprims = [(api.Prims.from_numpy(s.prims, dev), api.Rays.from_numpy(s.rays, dev)) for s in scenes]
     batch = api.Batch(grid, march, dprims, device=dev, min_chunk=4)
     rng = np.random.default_rng(1)
+    ups = []
     for i, s in enumerate(scenes):
         gd, gs = synth.upstream_grads(rng, s.rays, C)
-        batch.set_upstream(i, torch.from_numpy(gd).to(dev), torch.from_numpy(gs).to(dev))
+        ups.append((torch.from_numpy(gd).to(dev), torch.from_numpy(gs).to(dev)))
+        batch.set_upstream(i, *ups[i])
     R = batch.n_rays
     Ls = sc0.march.n_samples
     stream = torch.cuda.Stream(device=dev)
@@ -230,6 +232,7 @@ def main():
     t_idx = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     t_fwd = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     t_bwd = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    ref_out = [{k: batch.scene_outputs(i)[k].clone() for k in ("depth", "probs")} for i in range(len(scenes))]
 
     # the plain per-scene forward (no checkpoints) beside the differentiable and batched forms
     plain = []
@@ -289,6 +292,38 @@ def main():
         kappa_ms[f"{kappa:g}"] = dict(step_ms=step_k, fwd_ms=ke[0].elapsed_time(ke[1]) / args.steps)
     batch.set_kappa(0.0)
 
+    # influence-thresholded index (grid.theta): index size, step time and the change of the renders
+    theta_ab = {}
+    for theta in (1e-3, 1e-2):
+        gt = api.Grid(grid.lo, grid.voxel, grid.dims, grid.nv, theta)
+        bt = api.Batch(gt, march, dprims, device=dev, min_chunk=4)
+        for i in range(len(scenes)):
+            bt.set_upstream(i, *ups[i])
+        with torch.cuda.stream(stream):
+            bt.step(tune, stream=stream)
+        torch.cuda.synchronize()
+        et = sum(int(x) for x in bt.buf["totals"].cpu().tolist())
+        bt.capture(tune, stream=stream)
+        for _ in range(args.warmup):
+            bt.replay(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bt.replay(stream)
+        torch.cuda.synchronize()
+        step_t = (time.perf_counter() - t0) * 1e3 / args.steps
+        bt.release_graph()
+        dd, dp = 0.0, 0.0
+        for i in range(len(scenes)):
+            o = bt.scene_outputs(i)
+            d0 = ref_out[i]["depth"]
+            dd = max(dd, float(((o["depth"] - d0).abs() / d0.clamp_min(0.1)).max()))
+            dp = max(dp, float((o["probs"] - ref_out[i]["probs"]).abs().max()))
+        theta_ab[f"{theta:g}"] = dict(index_entries=et, step_ms=step_t, max_rel_depth_change=dd,
+                                      max_prob_change=dp)
+        del bt
+    torch.cuda.synchronize()
+
     # voxelisation of each scene's grid (Eq. eq:voxelisation, tau = 0.05) from the same index
     vox = [api.voxelise(grid, idx, p, tau=0.05) for p, r, idx, out in plain]
     torch.cuda.synchronize()
@@ -331,6 +366,7 @@ def main():
         "index_ms": t_idx, "fwd_ms": t_fwd, "bwd_ms": t_bwd, "plain_fwd_ms": t_plain,
         "index_entries": sum(E),
         "kappa_ms": kappa_ms,
+        "theta_index": theta_ab,
         "train_step_ms": ms_train,
         "train_ray_samples_per_s": R * Ls / (ms_train / 1e3),
         "train_loss": train_loss,
