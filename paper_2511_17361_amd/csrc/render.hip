@@ -46,8 +46,11 @@ int padded_classes(int C) {
 int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
 
 // Occupancy targets (waves per SIMD) that the register allocator must meet.
+// At 6 the persistent forward with checkpoints spills a few per-tile pointers
+// (stored at the tile's start, reloaded for its epilogue), which costs less
+// than the wave it buys.
 #define FWD_WPE(CP, CKPT, STATS, PERSIST) \
-    ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : !(CKPT) ? 6 : (PERSIST) ? 5 : 4)
+    ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : (!(CKPT) || (PERSIST)) ? 6 : 4)
 #define BWD_WPE(CP, KC) ((KC) == 4 && (CP) <= 17 ? 4 : 3)
 
 // Kernel parameters shared by every render kernel.
