@@ -148,7 +148,7 @@ typedef struct {
  *  waves_per_block  1..4.
  *  bwd_mode         SQ_BWD_AUTO picks the primitive-major backward where it
  *                   applies (checkpoint spacing 4 or 8, grid within
- *                   2047 x 2047 x 511, per-wave id bitmap within 64 KiB of LDS
+ *                   1023 x 1023 x 511, per-wave id bitmap within 64 KiB of LDS
  *                   per block) and the sample-major one otherwise; the other
  *                   values force one of them (forcing primitive-major where it
  *                   does not apply returns SQ_ERR_UNSUPPORTED).

@@ -115,8 +115,11 @@ __global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const 
     r[17] = is[0]; r[18] = is[1]; r[19] = is[2];
     int box[3];
     prim_box(g, means + 3 * k, quats + 4 * k, scales + 3 * k, eps + 2 * k, opacity + k, box);
-    r[20] = __int_as_float(box[0]); r[21] = __int_as_float(box[1]); r[22] = __int_as_float(box[2]);
-    r[23] = 0.0f;
+    uint32_t glo, hig;
+    box_words(box, glo, hig);
+    r[20] = __uint_as_float(glo); r[21] = __uint_as_float(hig);
+    r[22] = __int_as_float(box[0]); r[23] = __int_as_float(box[1]); r[24] = __int_as_float(box[2]);
+    r[25] = r[26] = r[27] = 0.0f;
     for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < C ? logits[(size_t)k * C + c] : 0.0f;
 }
 
@@ -324,24 +327,10 @@ __device__ __forceinline__ int clamp_list(int f0, int n0, int64_t cap) {
 //
 // The index lists primitive k in voxel v exactly when v lies in k's clipped
 // neighbourhood box (the packed box of its record), so a lane can test
-// membership of any primitive in its own voxel's list from the record alone.
-// A per-wave LDS bitmap with one bit per primitive of the scene enumerates the
-// union of several lists in ascending id.
+// membership of any primitive in its own voxel's list from the record alone
+// (in_box on the cell's packed word).  A per-wave LDS bitmap with one bit per
+// primitive of the scene enumerates the union of several lists in ascending id.
 // ---------------------------------------------------------------------------
-constexpr int PV_BITS_X = 11, PV_BITS_Y = 11;    // packed voxel: ix | iy << 11 | iz << 22
-constexpr int KM_MAX_XY = (1 << 11) - 1, KM_MAX_Z = (1 << 9) - 1;
-
-__device__ __forceinline__ int pack_voxel(int ix, int iy, int iz) {
-    return ix | (iy << PV_BITS_X) | (iz << (PV_BITS_X + PV_BITS_Y));
-}
-
-// k listed in packed voxel pv (pv < 0: dead sample)?
-__device__ __forceinline__ bool listed_in(int pv, int bx, int by, int bz) {
-    const int ix = pv & ((1 << PV_BITS_X) - 1);
-    const int iy = (pv >> PV_BITS_X) & ((1 << PV_BITS_Y) - 1);
-    const int iz = (int)((unsigned)pv >> (PV_BITS_X + PV_BITS_Y));
-    return (pv >= 0) & in_range(ix, bx) & in_range(iy, by) & in_range(iz, bz);
-}
 
 // Visit the set bits of a per-wave bitmap in ascending order (wave-uniform);
 // with CLEAR the words are zeroed as they are read.
@@ -454,14 +443,13 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                     pend = pend && (cur.v != vg);
                 }
                 wave_lds_sync();
+                // the union walk runs only on grids whose cells fit the packed form
+                const uint32_t cell = act ? pack_cell(cur.ix, cur.iy, cur.iz) : PV_DEAD;
                 for_each_marked<true>(bm, nw, lane, [&](int k) {
-                    Pinned<23> rr;
+                    Pinned<22> rr;
                     Pinned<CP> lg;
                     pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
-                    const bool mem = act & in_range(cur.ix, __float_as_int(rr[20])) &
-                                     in_range(cur.iy, __float_as_int(rr[21])) &
-                                     in_range(cur.iz, __float_as_int(rr[22]));
-                    if (mem) add_pair(k, rr, lg);
+                    if (in_box(cell, __float_as_uint(rr[20]), __float_as_uint(rr[21]))) add_pair(k, rr, lg);
                 });
                 wave_lds_sync();
             } else {
@@ -666,8 +654,8 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
         wave_lds_sync();
         for_each_marked<true>(bm, nw, lane, [&](int k) {
             const cf_ptr r = X.rec + (size_t)k * REC;
-            const bool mem = act && in_range(ix, __float_as_int(r[20])) && in_range(iy, __float_as_int(r[21])) &&
-                             in_range(iz, __float_as_int(r[22]));
+            const bool mem = act && in_range(ix, __float_as_int(r[22])) && in_range(iy, __float_as_int(r[23])) &&
+                             in_range(iz, __float_as_int(r[24]));
             if (mem) add_pair(k);
         });
     } else if (act) {
@@ -994,11 +982,11 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         for (int w = lane; w < nw; w += 64) bm[w] = 0u;
         wave_lds_sync();
         float sx[KC], sy[KC], sz[KC];
-        int pv[KC];
+        uint32_t pv[KC];     // packed cell of each sample (PV_DEAD: absent)
         int last_v = -1;
 #pragma unroll
         for (int jj = 0; jj < KC; ++jj) {
-            pv[jj] = -1;
+            pv[jj] = PV_DEAD;
             sx[jj] = sy[jj] = sz[jj] = 0.0f;
             if (j0 + jj < L) {
                 const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
@@ -1007,7 +995,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 int n = 0, f = 0;
                 bool act = (Tc > 0.0f) && (Tc >= kappa) && (sp.v >= 0);
                 if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
-                if (act) pv[jj] = pack_voxel(sp.ix, sp.iy, sp.iz);
+                if (act) pv[jj] = pack_cell(sp.ix, sp.iy, sp.iz);
                 bool pend = act;
                 uint64_t m;
                 while ((m = wave_ballot(pend)) != 0) {
@@ -1034,14 +1022,14 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
         for_each_marked(bm, nw, lane, [&](int k) {
             const cf_ptr r = X.rec + (size_t)k * REC;
-            Pinned<23> rr;
+            Pinned<22> rr;
             Pinned<CP> lg;
             pin2(r, rr, X.lgp + (size_t)k * CP, lg);
-            const int bx = __float_as_int(rr[20]), by = __float_as_int(rr[21]), bz = __float_as_int(rr[22]);
+            const uint32_t glo = __float_as_uint(rr[20]), hig = __float_as_uint(rr[21]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
-            for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
+            for (int jj = 0; jj < KC; ++jj) { mem[jj] = in_box(pv[jj], glo, hig); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
             float gam = 0.0f;
 #pragma unroll
@@ -1084,9 +1072,9 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 Q = fmaf(al, Gf, (1.0f - al) * Q);
                 const float da = (a[jj] < 1.0f) ? dal : 0.0f;
                 const float w = Tj[jj] * al;
-                if (STATS && pv[jj] >= 0) st[0] += 1;
-                if (!(Tj[jj] > 0.0f) || (da == 0.0f && w == 0.0f)) pv[jj] = -1;
-                if (STATS && pv[jj] >= 0) st[3] += 1;
+                if (STATS && pv[jj] != PV_DEAD) st[0] += 1;
+                if (!(Tj[jj] > 0.0f) || (da == 0.0f && w == 0.0f)) pv[jj] = PV_DEAD;
+                if (STATS && pv[jj] != PV_DEAD) st[3] += 1;
                 a[jj] = da;     // reuse: dL/da_j
                 G[jj] = w;      // reuse: w_j
             }
@@ -1095,14 +1083,14 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         // ---- pass 2: per-primitive adjoint over the union -------------------
         for_each_marked(bm, nw, lane, [&](int k) {
             const cf_ptr r = X.rec + (size_t)k * REC;
-            Pinned<23> rr;
+            Pinned<22> rr;
             Pinned<CP> lg;
             pin2(r, rr, X.lgp + (size_t)k * CP, lg);
-            const int bx = __float_as_int(rr[20]), by = __float_as_int(rr[21]), bz = __float_as_int(rr[22]);
+            const uint32_t glo = __float_as_uint(rr[20]), hig = __float_as_uint(rr[21]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
-            for (int jj = 0; jj < KC; ++jj) { mem[jj] = listed_in(pv[jj], bx, by, bz); anym |= mem[jj]; }
+            for (int jj = 0; jj < KC; ++jj) { mem[jj] = in_box(pv[jj], glo, hig); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
             float gam = 0.0f;
 #pragma unroll
@@ -1343,7 +1331,7 @@ __global__ __launch_bounds__(256) void k_sqm_prim_count(Ctx P, const int* __rest
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= P.desc->total_prims) return;
     const float* r = P.rec + (size_t)k * REC;
-    const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+    const int bx = __float_as_int(r[22]), by = __float_as_int(r[23]), bz = __float_as_int(r[24]);
     int64_t c = 0;
     if (bx != EMPTY_BOX)
         for (int ix = bx & 0xffff; ix <= (bx >> 16); ++ix)
@@ -1363,7 +1351,7 @@ __global__ __launch_bounds__(256) void k_sqm_prim_fill(Ctx P, const int* __restr
                                                        int64_t capacity) {
     const int k = blockIdx.x;
     const float* r = P.rec + (size_t)k * REC;
-    const int bx = __float_as_int(r[20]), by = __float_as_int(r[21]), bz = __float_as_int(r[22]);
+    const int bx = __float_as_int(r[22]), by = __float_as_int(r[23]), bz = __float_as_int(r[24]);
     if (bx == EMPTY_BOX) return;
     int64_t pos = off[k];
     for (int ix = bx & 0xffff; ix <= (bx >> 16); ++ix)
@@ -1666,6 +1654,8 @@ static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, co
     return P;
 }
 
+// Grids whose cells fit the packed form of in_box.
+static bool cells_fit(const GridDev& g) { return g.X <= PV_MAX_XY && g.Y <= PV_MAX_XY && g.Z <= PV_MAX_Z; }
 // LDS budget of the per-wave bitmaps of one block.
 static bool bitmap_fits(int max_n, int wpb) {
     return (size_t)wpb * bitmap_words(max_n) * sizeof(uint32_t) <= 64 * 1024;
@@ -1696,7 +1686,8 @@ static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
     prep_records<CP>(d, g, io, l, st);
     const int wpb = t.waves_per_block;
     Ctx P = P0;
-    if (!bitmap_fits(d.max_n, wpb)) P.bitmap_words = 0;
+    // the union walk tests membership on packed cells
+    if (!bitmap_fits(d.max_n, wpb) || !cells_fit(g)) P.bitmap_words = 0;
     const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);
     const bool ck = P.ckpt != nullptr, stt = P.stats != nullptr;
     if (loss) {
@@ -1872,7 +1863,7 @@ hipError_t launch_batch_bwd_sq_major(const GridDev& g, const BatchDesc& d, const
 // packed form.  Otherwise the sample-major backward runs.
 bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb) {
     if (!(K == 4 || K == 8)) return false;
-    if (g.X > KM_MAX_XY || g.Y > KM_MAX_XY || g.Z > KM_MAX_Z) return false;
+    if (!cells_fit(g)) return false;
     // sized for the largest per-wave scratch (C = 17), whatever C is
     return km_lds_bytes(bitmap_words(max_n), wpb, 17) <= 64 * 1024;
 }

@@ -20,11 +20,13 @@ namespace sqr {
 //   [15]     sigma
 //   [16]     r_cull: max(|u|,|v|,|w|) >= r_cull  =>  f >= F_CULL
 //   [17..19] 1/s
-//   [20..22] clipped neighbourhood box per axis, int bits lo | hi << 16
+//   [20..21] the same box as [22..24] in the packed-cell form of box_words
+//            (int bits; meaningful on grids within PV_MAX_XY x PV_MAX_XY x PV_MAX_Z)
+//   [22..24] clipped neighbourhood box per axis, int bits lo | hi << 16
 //            (the primitive is listed in voxel v iff v lies in this box)
-//   [23]     unused
+//   [25..27] unused
 // ---------------------------------------------------------------------------
-constexpr int REC = 24;
+constexpr int REC = 28;
 constexpr int EMPTY_BOX = 0x7fff7fff;
 constexpr float F_CULL = 110.0f;          // exp(-110) = 1.7e-48: 0 in float32
 constexpr float LOG2E = 1.4426950408889634f;
@@ -386,6 +388,42 @@ __device__ __forceinline__ void prim_box(const GridDev& g, const float* m, const
 __device__ __forceinline__ bool in_range(int i, int packed) {
     const int lo = packed & 0xffff, hi = packed >> 16;
     return (unsigned)(i - lo) <= (unsigned)(hi - lo);
+}
+
+// Voxel cells packed into one word, x | y << 11 | z << 22, with a guard bit
+// above each field (bits 10, 21, 31).  The three-axis box test then takes two
+// subtractions and one and-or: for a cell word c with clear guards,
+//   c + (G - lo) keeps a field's guard bit set exactly when c_f >= lo_f,
+//   (hi | G) - c keeps it set exactly when c_f <= hi_f,
+// and no borrow or carry crosses a guard.  Grids up to PV_MAX_XY x PV_MAX_XY x
+// PV_MAX_Z cells fit; PV_DEAD (every field at its maximum, above any cell of
+// such a grid) lies in no box.
+constexpr uint32_t PV_GUARDS = (1u << 10) | (1u << 21) | (1u << 31);
+constexpr int PV_MAX_XY = 1023, PV_MAX_Z = 511;
+constexpr uint32_t PV_DEAD = 0x3ffu | (0x3ffu << 11) | (0x1ffu << 22);
+
+__device__ __forceinline__ uint32_t pack_cell(int ix, int iy, int iz) {
+    return (uint32_t)ix | ((uint32_t)iy << 11) | ((uint32_t)iz << 22);
+}
+// The record words of a per-axis box (prim_box's output): G - lo and hi | G.
+// An empty box gets lo above hi in every field, which no cell satisfies.
+__device__ __forceinline__ void box_words(const int box[3], uint32_t& glo, uint32_t& hig) {
+    int lo[3], hi[3];
+    bool empty = false;
+    const int cap[3] = {PV_MAX_XY, PV_MAX_XY, PV_MAX_Z};
+    for (int ax = 0; ax < 3; ++ax) {
+        lo[ax] = box[ax] & 0xffff;
+        hi[ax] = box[ax] >> 16;
+        empty |= box[ax] == EMPTY_BOX || lo[ax] > hi[ax] || hi[ax] >= cap[ax];
+    }
+    const uint32_t plo = empty ? PV_DEAD : pack_cell(lo[0], lo[1], lo[2]);
+    const uint32_t phi = empty ? 0u : pack_cell(hi[0], hi[1], hi[2]);
+    glo = PV_GUARDS - plo;
+    hig = phi | PV_GUARDS;
+}
+// Cell word c (guards clear) inside the box of record words glo, hig?
+__device__ __forceinline__ bool in_box(uint32_t c, uint32_t glo, uint32_t hig) {
+    return (((c + glo) & (hig - c)) | ~PV_GUARDS) == 0xffffffffu;
 }
 
 }  // namespace sqr

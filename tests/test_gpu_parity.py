@@ -243,3 +243,38 @@ def test_bwd_config2_sparse_upstream(mode):
     _, g = H.run_fwd_bwd(sc, g_d_img, g_s_img, tuning=api.Tuning(8, 4, mode))
     ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d[ids], g_s[ids], ray_ids=ids)
     H.assert_grads_close(g, ref, "cfg2")
+
+
+def _long_grid_scene(dims, voxel, lo, centres, pitch):
+    """A column-shaped grid longer than the packed cell form holds (1023 cells
+    along x or y, 511 along z), primitives strung along its axis and a narrow
+    camera at the origin looking down it."""
+    rng = np.random.Generator(np.random.PCG64(61))
+    grid = synth.Grid(lo=lo, voxel=voxel, dims=dims, nv=2)
+    prims = synth.make_prims(rng, np.asarray(centres, np.float64), 0.05, 0.15, 5)
+    rays = synth.pinhole_rig(1, 16, 12, 2.0, (0.0, 0.0, 0.0), pitch_deg=pitch)
+    return synth.Scene(grid, prims, rays, synth.March(64, 0.1, 12.0), name="long")
+
+
+@pytest.mark.parametrize("axis", ["x", "z"])
+def test_grids_beyond_packed_cells(axis):
+    """Such grids do not fit the packed-cell membership test: the forward walks
+    one voxel group at a time and the backward runs sample-major.  Both still
+    match the oracle, and forcing the primitive-major backward is refused."""
+    t = np.linspace(1.0, 10.0, 24)
+    if axis == "x":
+        sc = _long_grid_scene((1100, 8, 8), 0.05, (-0.5, -0.2, -0.2), np.stack([t, 0 * t, 0 * t], 1), 0.0)
+    else:
+        sc = _long_grid_scene((8, 8, 600), 0.05, (-0.2, -0.2, -0.5), np.stack([0 * t, 0 * t, t], 1), 90.0)
+    _say("grid beyond packed cells", axis, sc.grid.dims)
+    C = sc.prims.n_classes
+    rng = np.random.default_rng(61)
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, C)
+    out, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=4, tuning=api.Tuning(8, 2))
+    ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march)
+    assert np.count_nonzero(ref["depth"] > 0.5) > 20, "the camera must see the primitives"
+    H.assert_depth_close(out["depth"], ref["depth"], f"long {axis}")
+    H.assert_probs_close(out["probs"], ref["probs"], f"long {axis}")
+    H.assert_grads_close(g, oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s), f"long {axis}")
+    with pytest.raises(Exception, match="status -4"):
+        H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=4, tuning=api.Tuning(8, 2, 2))
