@@ -1098,8 +1098,23 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             const float sig = rr[15];
             constexpr int VR = SPLIT ? 16 : VP;     // values reduced across the wave
             float x[VR];
+            // At C = 17 the 16 sums are zeroed through an opaque move: a plain 0
+            // is rematerialised after the first sample's evaluation, a second
+            // set of 16 moves per (chunk, primitive).  The wider rows of the
+            // other class counts would hold too many registers that way.
+            if constexpr (SPLIT) {
+                // pairs of sums cleared by one 64-bit move each
 #pragma unroll
-            for (int i = 0; i < VR; ++i) x[i] = 0.0f;
+                for (int i = 0; i < VR; i += 2) {
+                    uint64_t z2;
+                    asm volatile("v_mov_b64 %0, 0" : "=v"(z2));
+                    x[i] = __uint_as_float((uint32_t)z2);
+                    x[i + 1] = __uint_as_float((uint32_t)(z2 >> 32));
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < VR; ++i) x[i] = 0.0f;
+            }
             float om = 0.0f;          // sum_j w_j p_jk
             bool contrib = false;
 #pragma unroll
