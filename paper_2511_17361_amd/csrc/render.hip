@@ -389,6 +389,9 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
             if (alive && nxt.v >= 0) { n_nxt = X.counts[nxt.v]; f_nxt = X.offsets[nxt.v]; }
         }
         if (CKPT && (j % K) == 0 && rl.valid) ckpt[(int64_t)(j / K) * R] = T;
+        // a ray that has left the grid for good adds nothing more; once every
+        // lane has, the tile stops as it does when all rays are opaque
+        if ((j & 3) == 0) alive = alive && !left_grid(P.g, cur, rl.dx, rl.dy, rl.dz);
 
         const bool act = alive && (cur.v >= 0) && (n > 0);
         const uint64_t am = wave_ballot(act);
@@ -977,6 +980,12 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         const float Tc = rl.valid ? ckpt[(int64_t)ci * R + lane_lray(rl, S)] : 0.0f;
         if (wave_ballot((Tc > 0.0f) && (Tc >= kappa)) == 0) continue;
         const int j0 = ci * KC;
+        {
+            // a ray that left the grid for good before the chunk adds nothing in it
+            const SamplePos s0 = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0, rl.ox, rl.oy, rl.oz, rl.dx, rl.dy,
+                                               rl.dz);
+            if (wave_ballot((Tc > 0.0f) && (Tc >= kappa) && !left_grid(P.g, s0, rl.dx, rl.dy, rl.dz)) == 0) continue;
+        }
 
         // ---- chunk geometry + bitmap of the listed ids ----------------------
         for (int w = lane; w < nw; w += 64) bm[w] = 0u;

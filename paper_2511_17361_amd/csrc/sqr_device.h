@@ -87,6 +87,22 @@ __device__ __forceinline__ SamplePos pinned_sample(const GridDev& g, float t_nea
     return s;
 }
 
+// Sample s lies outside the grid along an axis on which the ray moves away from
+// (or parallel to) the grid: every later sample of the ray lies outside too.
+// Each step of pinned_sample is a monotone function of j (of t, then of x for
+// a fixed sign of d), so a cell coordinate that has left [0, dims) in the
+// direction of travel never comes back.  The same op sequence as
+// pinned_sample, so the test sees the very q it classified.
+__device__ __forceinline__ bool left_grid(const GridDev& g, const SamplePos& s, float dx, float dy, float dz) {
+#pragma clang fp contract(off)
+    const float qx = (s.x - g.lox) * g.inv;
+    const float qy = (s.y - g.loy) * g.inv;
+    const float qz = (s.z - g.loz) * g.inv;
+    return ((qx >= (float)g.X) & (dx >= 0.0f)) | ((qx < 0.0f) & (dx <= 0.0f)) |
+           ((qy >= (float)g.Y) & (dy >= 0.0f)) | ((qy < 0.0f) & (dy <= 0.0f)) |
+           ((qz >= (float)g.Z) & (dz >= 0.0f)) | ((qz < 0.0f) & (dz <= 0.0f));
+}
+
 // Centre of voxel i along one axis in float32, fl(lo + fl(fl(i + 0.5) * voxel))
 // with no fused multiply-add (the point the voxelisation evaluates).
 __device__ __forceinline__ float pinned_voxel_centre(float lo, float vs, int i) {

@@ -278,3 +278,32 @@ def test_grids_beyond_packed_cells(axis):
     H.assert_grads_close(g, oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s), f"long {axis}")
     with pytest.raises(Exception, match="status -4"):
         H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=4, tuning=api.Tuning(8, 2, 2))
+
+
+@pytest.mark.parametrize("cam,yaw,pitch", [((-6.0, 0.3, 0.2), 0.0, 0.0), ((0.5, -0.5, 0.0), 180.0, 30.0),
+                                           ((0.0, 5.0, -0.3), -90.0, -20.0)])
+def test_rays_entering_and_leaving_the_grid(cam, yaw, pitch):
+    """Rays that start outside the grid and enter it later, rays that leave it
+    through every face, and rays that miss it: the forward stops a ray once it
+    has left the grid for good and the backward skips such chunks, which must
+    not change any output."""
+    rng = np.random.Generator(np.random.PCG64(71))
+    grid = synth.Grid(lo=(-2.0, -2.0, -1.0), voxel=0.25, dims=(16, 16, 8), nv=3)
+    means = rng.uniform((-1.8, -1.8, -0.8), (1.8, 1.8, 0.8), (40, 3))
+    prims = synth.make_prims(rng, means, 0.1, 0.5, 4)
+    prims.opacity[:] = (prims.opacity * 0.3).astype(np.float32)
+    rays = synth.pinhole_rig(1, 24, 20, 100.0, cam, yaw0_deg=yaw, pitch_deg=pitch)
+    sc = synth.Scene(grid, prims, rays, synth.March(90, 0.1, 14.0), name="in-out")
+    _say("rays entering and leaving", cam, yaw, pitch)
+    g_d, g_s = synth.upstream_grads(np.random.default_rng(71), sc.rays, 4)
+    out, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=4, tuning=api.Tuning(8, 2))
+    ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march)
+    assert np.count_nonzero(ref["depth"] > 0) > 0
+    H.assert_depth_close(out["depth"], ref["depth"], "in-out")
+    H.assert_probs_close(out["probs"], ref["probs"], "in-out")
+    H.assert_tfinal_close(out["t_final"], ref["t_final"], "in-out")
+    H.assert_grads_close(g, oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s), "in-out")
+    # the checkpoints still hold T at every chunk start after a ray has left
+    ck = out["ckpt"]
+    assert np.all(np.diff(ck, axis=0) <= 0)
+    assert np.all(ck[-1] >= out["t_final"].reshape(-1))
