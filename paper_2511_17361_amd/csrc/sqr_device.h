@@ -125,7 +125,7 @@ __device__ __forceinline__ int pinned_centre_axis(float m, float lo, float inv, 
 // compiler keeps it in its register instead of re-issuing the scalar load
 // (and waiting for it) at every use, and the loads of one group are issued
 // together behind a single wait.  A record needs its first 17 entries for the
-// pair evaluation, 23 with the clipped box.
+// pair evaluation, 22 with the packed-cell box words.
 template <int N>
 struct Pinned {
     float v[N];
