@@ -161,6 +161,48 @@ def sq_major_ab(dev, steps, K=4):
                 atomics_ms=t_atomic, sq_major_ms=t_sqm)
 
 
+def batched_8_scenes(dev, steps, warmup):
+    """The batched training step over the 8 scenes of uneven size (2k .. 25.6k
+    superquadrics, 94k in all; 6 cameras x 352x200 rays each, L = 100), with the
+    tuning chosen by the autotuner, captured once and replayed."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2511_17361_amd import api
+    scenes = [synth.config(3, s) for s in range(8)]
+    sc0 = scenes[0]
+    grid = api.Grid.of(sc0.grid)
+    march = api.March(sc0.march.n_samples, sc0.march.t_near, sc0.march.t_far, 4)
+    dprims = [(api.Prims.from_numpy(s.prims, dev), api.Rays.from_numpy(s.rays, dev)) for s in scenes]
+    batch = api.Batch(grid, march, dprims, device=dev, min_chunk=4)
+    rng = np.random.default_rng(3)
+    for i, s in enumerate(scenes):
+        gd, gs = synth.upstream_grads(rng, s.rays, s.prims.n_classes)
+        batch.set_upstream(i, torch.from_numpy(gd).to(dev), torch.from_numpy(gs).to(dev))
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        tune, _ = batch.autotune(api.default_candidates(), reps=1, stream=stream)
+    torch.cuda.synchronize()
+    batch.capture(tune, stream=stream)
+    for _ in range(warmup):
+        batch.replay(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.replay(stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    batch.release_graph()
+    samples = batch.n_rays * sc0.march.n_samples
+    return dict(workload="8 scenes, 2k..25.6k superquadrics (94k), 6 cameras x 352x200 rays each, L=100, "
+                         "step = index + forward(checkpoints) + backward, autotuned, one hipGraph replay",
+                superquadrics=sum(s.prims.n for s in scenes), rays=batch.n_rays, step_ms=ms,
+                ray_samples_per_s=samples / (ms / 1e3),
+                tuning=dict(tile_w=tune.tile_w, waves_per_block=tune.waves_per_block, bwd_mode=tune.bwd_mode,
+                            persistent=tune.persistent, chunk=tune.chunk))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -403,6 +445,7 @@ def main():
                               "frac_nonpacked": ach / VALU_NONPACKED_TFLOPS}
 
     result["sq_major_ab"] = sq_major_ab(dev, args.steps)
+    result["batched_8_scenes"] = batched_8_scenes(dev, args.steps, args.warmup)
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
