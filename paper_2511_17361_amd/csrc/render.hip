@@ -988,8 +988,8 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         }
 
         // ---- chunk geometry + bitmap of the listed ids ----------------------
-        for (int w = lane; w < nw; w += 64) bm[w] = 0u;
-        wave_lds_sync();
+        // (the bitmap is clear here: cleared at the start, and pass 2 clears
+        // every word it reads)
         float sx[KC], sy[KC], sz[KC];
         uint32_t pv[KC];     // packed cell of each sample (PV_DEAD: absent)
         int last_v = -1;
@@ -1044,6 +1044,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
             for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
             const float sig = rr[15];
+            bool hit = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
                 if (mem[jj]) {
@@ -1052,9 +1053,13 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                     if (p != 0.0f) {
                         a[jj] = fmaf(p, sig, a[jj]);
                         G[jj] = fmaf(p, gam, G[jj]);
+                        hit = true;
                     }
                 }
             }
+            // p = 0 for every lane and sample: the adjoint of k is 0 in this
+            // chunk, so pass 2 need not visit it
+            if (wave_ballot(hit) == 0 && lane == 0) bm[k >> 5] &= ~(1u << (k & 31));
         });
 
         // ---- compositing and its adjoint (per lane) -------------------------
@@ -1090,7 +1095,8 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         }
 
         // ---- pass 2: per-primitive adjoint over the union -------------------
-        for_each_marked(bm, nw, lane, [&](int k) {
+        wave_lds_sync();
+        for_each_marked<true>(bm, nw, lane, [&](int k) {
             const cf_ptr r = X.rec + (size_t)k * REC;
             Pinned<22> rr;
             Pinned<CP> lg;
@@ -1194,6 +1200,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
     // per-wave logit scratch after the block's bitmaps (C = 17 only)
     float* lgs = reinterpret_cast<float*>(bm_all + (size_t)(blockDim.x >> 6) * P.bitmap_words) +
                  (size_t)wave * LGS_FLOATS;
+    // one clear per wave: every chunk's second pass clears the words it reads
+    for (int w = (int)(threadIdx.x & 63); w < P.bitmap_words; w += 64) bm[w] = 0u;
+    wave_lds_sync();
     for_each_tile<PERSIST>(P, [&](int t, const Ctx& Q) {
         const int s = find_scene(Q.desc, t);
         bwd_km_tile<CP, KC, STATS>(Q, s, t - Q.desc->s[s].tile_off, bm, lgs);
