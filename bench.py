@@ -57,9 +57,14 @@ def flops_fwd(st, C):
     return 24 * listed + (16 + 2 * C) * evaluated + (23 + 7 + 2 * C) * samples
 
 
-def flops_bwd(fst, bst, C):
+def flops_bwd(fst, C):
+    """Algorithmic FLOPs of the backward over the method's own (sample,
+    primitive) pairs, the forward's counts: the recompute and the adjoint each
+    cover every listed pair of every live sample once.  Work the kernel skips
+    because it is provably zero (samples past a ray's end in pass 1, primitives
+    with p = 0 throughout a chunk in pass 2) is neither added nor removed."""
     recompute = 24 * fst["listed"] + (20 + 2 * C) * fst["evaluated"] + (23 + 7 + 2 * C) * fst["samples"]
-    adjoint = 24 * bst["listed2"] + (112 + 3 * C) * bst["eval2"] + (23 + 10) * bst["samples2"]
+    adjoint = 24 * fst["listed"] + (112 + 3 * C) * fst["evaluated"] + (23 + 10) * fst["samples"]
     return recompute + adjoint
 
 
@@ -435,7 +440,7 @@ def main():
         result["fwd_tflops"] = flops_fwd(fst, C) / (t_fwd / 1e3) / 1e12
         result["fwd_roofline_frac"] = result["fwd_tflops"] / VALU_PEAK_TFLOPS
         result["fwd_roofline_frac_nonpacked"] = result["fwd_tflops"] / VALU_NONPACKED_TFLOPS
-        f_bwd = flops_bwd(fst, b, C)
+        f_bwd = flops_bwd(fst, C)
         ach = f_bwd / (t_bwd / 1e3) / 1e12
         kname = f"sqr::k_render_bwd_km<{api_cp(C)}, {K}, false, {'true' if tune.persistent else 'false'}>"
         result["roofline"] = {"bound": "alu", "kernel": kname, "achieved": ach, "peak": VALU_PEAK_TFLOPS,
