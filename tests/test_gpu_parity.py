@@ -307,3 +307,59 @@ def test_rays_entering_and_leaving_the_grid(cam, yaw, pitch):
     ck = out["ckpt"]
     assert np.all(np.diff(ck, axis=0) <= 0)
     assert np.all(ck[-1] >= out["t_final"].reshape(-1))
+
+
+def test_config2_gradients_against_central_differences():
+    """Config 2 asks for central differences on 200 random visible parameters.
+    Upstream gradients sit on 64 rays only, so each difference renders just those
+    rays with the FP64 oracle (h = 1e-4); the GPU gradient must match within
+    1e-3 |g| + 1e-3 rms(g) of its group.  A parameter whose difference changes
+    between h and h/2 straddles a kink (the alpha clamp, a list change) and is
+    skipped, as is a centre moved into another voxel."""
+    sc = synth.config(2)
+    C = sc.prims.n_classes
+    rng = np.random.default_rng(9)
+    ids = rng.choice(sc.rays.n_rays, 64, replace=False)
+    g_d = np.zeros(sc.rays.n_rays, np.float32)
+    g_s = np.zeros((sc.rays.n_rays, C), np.float32)
+    g_d[ids] = rng.standard_normal(ids.size).astype(np.float32)
+    g_s[ids] = rng.standard_normal((ids.size, C)).astype(np.float32)
+    cams, Hh, Ww = sc.rays.shape
+    _say("config2 central differences")
+    _, g = H.run_fwd_bwd(sc, g_d.reshape(cams, Hh, Ww),
+                         g_s.reshape(cams, Hh, Ww, C).transpose(0, 3, 1, 2).copy(), tuning=api.Tuning(8, 2))
+    index = oracle.build_index(sc.prims, sc.grid)[:3]
+    names = ("means", "quats", "scales", "eps", "opacity", "logits")
+    base = {k: np.asarray(getattr(sc.prims, k), np.float64) for k in names}
+    rms = {k: float(np.sqrt(np.mean(np.square(g[k].astype(np.float64))))) for k in names}
+    cand = [(k, i) for k in names for i in np.flatnonzero(np.abs(g[k].reshape(-1)) > 1e-3 * rms[k])]
+    pick = [cand[i] for i in rng.choice(len(cand), 200, replace=False)]
+    inv = np.float32(1.0) / np.float32(sc.grid.voxel)
+    lo = np.asarray(sc.grid.lo, np.float32)
+
+    def loss(name, i, dx):
+        arrs = {k: base[k].copy() for k in names}
+        arrs[name].reshape(-1)[i] += dx
+        pr = synth.Prims(*(arrs[k] for k in names))
+        out = oracle.render(sc.grid, pr, sc.rays, sc.march, index=index, ray_ids=ids)
+        return oracle.loss_value(out, g_d[ids], g_s[ids])
+
+    def cell(m):
+        return np.floor((np.float32(m) - lo) * inv)
+
+    h = 1e-4
+    checked = 0
+    for name, i in pick:
+        if name == "means":
+            k, ax = divmod(int(i), 3)
+            m = base["means"][k, ax]
+            if cell(m + h)[ax] != cell(m - h)[ax] or cell(m + h)[ax] != cell(m)[ax]:
+                continue
+        fd = (loss(name, i, h) - loss(name, i, -h)) / (2 * h)
+        fd2 = (loss(name, i, h / 2) - loss(name, i, -h / 2)) / h
+        if abs(fd - fd2) > 1e-4 * abs(fd) + 1e-6 * rms[name]:
+            continue
+        got = float(g[name].reshape(-1)[i])
+        assert abs(got - fd) <= 1e-3 * abs(fd) + 1e-3 * rms[name], (name, int(i), got, fd)
+        checked += 1
+    assert checked >= 180, checked
