@@ -354,10 +354,28 @@ typedef struct {
     const int32_t *sem_label;
     const float *depth_label;
     float *loss;
+    /* Where each ray tile of the last forward stopped (nullable; an
+     * MI355X-side design choice, not in the paper).  A forward with
+     * checkpoints writes, for every tile t of its tiling, tile_stop[4 + t] =
+     * the last sample it composited before every ray of the tile was opaque
+     * or out of the grid (L - 1 when the march ran to the end), behind a
+     * header [tile width, L, K, 1]; a forward without checkpoints writes the
+     * header with 0 in place of the 1.  The primitive-major backward, given
+     * the buffer, skips the samples past each tile's stop (they add nothing);
+     * when the header does not match its own tiling and march it ignores the
+     * buffer.  Like the checkpoints, the buffer belongs to the last forward:
+     * pass it to both calls or to neither.  tile_stop holds tile_stop_len
+     * int32, at least sq_batch_tile_stop_len(); shorter: SQ_ERR_CAPACITY. */
+    int32_t *tile_stop;
+    int64_t  tile_stop_len;
 } sq_batch_io;
 
 /* Bytes of workspace every batched call needs (host-only; 0 on bad input). */
 size_t sq_batch_workspace(const sq_batch* batch);
+
+/* Length (int32) of io->tile_stop for calls with this tuning (its tile width;
+ * NULL = defaults).  Host-only; 0 on bad input. */
+int64_t sq_batch_tile_stop_len(const sq_batch* batch, const sq_tuning* tuning);
 
 /* sq_build_index for every scene of the batch (Sec. 3.3 "Preliminary
  * Construction").  Writes counts, offsets, ids (below each scene's capacity)

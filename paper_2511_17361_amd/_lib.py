@@ -26,7 +26,7 @@ EXPORTED = [
     "sq_batch_step_graph_create", "sq_graph_launch", "sq_graph_destroy", "sq_batch_autotune",
     "sq_voxelise_workspace", "sq_voxelise", "sq_batch_voxelise",
     "sq_render_fwd_loss", "sq_batch_render_fwd_loss", "sq_batch_train_step", "sq_batch_train_graph_create",
-    "sq_sq_major_workspace", "sq_render_bwd_sq_major",
+    "sq_sq_major_workspace", "sq_render_bwd_sq_major", "sq_batch_tile_stop_len",
 ]
 
 
@@ -88,7 +88,8 @@ class SqBatchIO(ct.Structure):
         "means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs",
         "counts", "offsets", "ids", "totals", "depth", "sem", "probs", "t_final", "ckpt",
         "g_depth", "g_sem", "g_means", "g_quats", "g_scales", "g_eps", "g_opacity", "g_logits",
-        "vox_density", "vox_sem", "vox_labels", "sem_label", "depth_label", "loss")]
+        "vox_density", "vox_sem", "vox_labels", "sem_label", "depth_label", "loss", "tile_stop")] + [
+        ("tile_stop_len", ct.c_int64)]
 
 
 class SqLossWeights(ct.Structure):
@@ -129,6 +130,8 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
                                   ct.c_void_p, ct.c_size_t, ct.c_void_p]
     lib.sq_batch_workspace.restype = ct.c_size_t
     lib.sq_batch_workspace.argtypes = [P(SqBatch)]
+    lib.sq_batch_tile_stop_len.restype = ct.c_int64
+    lib.sq_batch_tile_stop_len.argtypes = [P(SqBatch), P(SqTuning)]
     lib.sq_batch_build_index.restype = ct.c_int32
     lib.sq_batch_build_index.argtypes = [P(SqBatch), P(SqBatchIO), ct.c_void_p, ct.c_size_t, ct.c_void_p]
     for fn in (lib.sq_batch_render_fwd, lib.sq_batch_render_bwd):

@@ -337,7 +337,7 @@ def render_bwd_stats(grid, index: Index, prims: Prims, rays: Rays, march, ckpt, 
 _IO_FIELDS = ("means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs", "counts", "offsets", "ids",
               "totals", "depth", "sem", "probs", "t_final", "ckpt", "g_depth", "g_sem", "g_means", "g_quats",
               "g_scales", "g_eps", "g_opacity", "g_logits", "vox_density", "vox_sem", "vox_labels", "sem_label",
-              "depth_label", "loss")
+              "depth_label", "loss", "tile_stop")
 
 # Loss weights of the paper (Supplement "Loss Formulation"): lambda_s = 2, lambda_d = 0.05.
 PAPER_LOSS = (2.0, 0.05)
@@ -470,6 +470,10 @@ class Batch:
                         g_depth=z(R), g_sem=z(R * C))
         for k in ("means", "quats", "scales", "eps", "opacity", "logits"):
             self.buf["g_" + k] = torch.zeros_like(getattr(self.prims, k))
+        # where each ray tile's forward stopped, sized for every tile width
+        n_stop = max(int(lib.sq_batch_tile_stop_len(ct.byref(b), ct.byref(Tuning(tile_w=tw).c())))
+                     for tw in (4, 8, 16))
+        self.buf["tile_stop"] = torch.zeros(n_stop, dtype=torch.int32, device=device)
         self.ws = _workspace(lib.sq_batch_workspace(ct.byref(b)), device)
         self.graph = None
 
@@ -485,6 +489,8 @@ class Batch:
         vals["origins"], vals["dirs"] = self.origins, self.dirs
         for name in _IO_FIELDS:
             setattr(io, name, _ptr(vals.get(name)))
+        if vals.get("tile_stop") is not None:
+            io.tile_stop_len = int(vals["tile_stop"].numel())
         return io
 
     def _call(self, fn, *args):

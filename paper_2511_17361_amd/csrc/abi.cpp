@@ -199,6 +199,7 @@ sqr::BatchIO to_dev(const sq_batch_io* io) {
     b.g_opacity = io->g_opacity; b.g_logits = io->g_logits;
     b.vox_density = io->vox_density; b.vox_sem = io->vox_sem; b.vox_labels = io->vox_labels;
     b.sem_label = io->sem_label; b.depth_label = io->depth_label; b.loss = io->loss;
+    b.tile_stop = io->tile_stop;
     return b;
 }
 
@@ -213,6 +214,16 @@ sq_status index_checked(const Plan& p, const sq_batch_io* io, void* ws, size_t w
     return hip_status(sqr::launch_batch_index(p.g, p.d, to_dev(io), ws, stream), "build_index");
 }
 
+// The per-tile stops (nullable): a header and one entry per tile of this tiling.
+sq_status check_tile_stop(const Plan& p, const sq_batch_io* io) {
+    if (!io->tile_stop) return SQ_OK;
+    const int64_t need = 4 + (int64_t)p.d.total_tiles;
+    if (io->tile_stop_len < need)
+        return fail(SQ_ERR_CAPACITY, "tile_stop_len %lld < %lld for this tiling", (long long)io->tile_stop_len,
+                    (long long)need);
+    return SQ_OK;
+}
+
 sq_status fwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, const sq_tuning* tuning, void* ws,
                       size_t ws_bytes, hipStream_t stream) {
     sq_status s;
@@ -221,6 +232,7 @@ sq_status fwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
         return fail(SQ_ERR_INVALID, "depth/sem/t_final is NULL");
     const int K = chunk_of(tuning, p.m);
     if (io->ckpt && K < 1) return fail(SQ_ERR_INVALID, "ckpt given but the checkpoint spacing is < 1");
+    if ((s = check_tile_stop(p, io))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
     if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
@@ -240,6 +252,7 @@ sq_status bwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
     if (p.d.total_prims > 0 && (!io->g_means || !io->g_quats || !io->g_scales || !io->g_eps || !io->g_opacity ||
                                 !io->g_logits))
         return fail(SQ_ERR_INVALID, "a gradient output array is NULL");
+    if ((s = check_tile_stop(p, io))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
     if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
@@ -272,6 +285,7 @@ sq_status fwd_loss_checked(const Plan& p, const sq_batch_io* io, const sq_loss_w
     if ((s = check_loss(p, io, w))) return s;
     const int K = chunk_of(tuning, p.m);
     if (io->ckpt && K < 1) return fail(SQ_ERR_INVALID, "ckpt given but the checkpoint spacing is < 1");
+    if ((s = check_tile_stop(p, io))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
     if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
@@ -359,7 +373,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 205; }
+int32_t sq_version(void) { return 206; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
@@ -570,6 +584,14 @@ sq_status sq_voxelise(const sq_grid* grid, const sq_index* idx, const sq_prims* 
 }
 
 // ---- batched -------------------------------------------------------------------
+int64_t sq_batch_tile_stop_len(const sq_batch* b, const sq_tuning* tuning) {
+    sqr::TuneDev tune;
+    if (tuning_of(tuning, tune)) return 0;
+    Plan p;
+    if (make_plan(b, tune.tile_w, p)) return 0;
+    return 4 + (int64_t)p.d.total_tiles;
+}
+
 size_t sq_batch_workspace(const sq_batch* b) {
     Plan p;
     if (make_plan(b, 4, p)) return 0;

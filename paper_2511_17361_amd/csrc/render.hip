@@ -79,7 +79,12 @@ struct Ctx {
     float lam_s, lam_d;
     const int* lcount;          // labelled pixels: semantic, depth
     float* lpart;               // per-tile partial sums (cross-entropy, squared error)
+    // nullable: [0] tile width, [1] L, [2] K, [3] 1 once a forward with
+    // checkpoints wrote it, then per global tile the last sample its forward
+    // composited
+    int* tile_stop;
 };
+constexpr int STOP_HEAD = 4;
 
 // ---------------------------------------------------------------------------
 // Per-primitive preparation (all primitives of the batch)
@@ -126,6 +131,14 @@ __global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const 
 __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, float v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// Header of the per-tile stops before a forward: its tiling and march, and
+// whether it writes the stops (a forward with checkpoints).
+__global__ __launch_bounds__(64) void k_stop_header(int* __restrict__ tab, int tile_w, int L, int K, int written) {
+    if (threadIdx.x == 0) {
+        tab[0] = tile_w; tab[1] = L; tab[2] = K; tab[3] = written;
+    }
 }
 
 __global__ __launch_bounds__(64) void k_fill_int(int* __restrict__ p, int n, int v) {
@@ -379,6 +392,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
     SamplePos nxt = pinned_sample(P.g, P.mr.t_near, P.mr.delta, 0, rl.ox, rl.oy, rl.oz, rl.dx, rl.dy, rl.dz);
     int n_nxt = 0, f_nxt = 0;
     if (alive && nxt.v >= 0) { n_nxt = X.counts[nxt.v]; f_nxt = X.offsets[nxt.v]; }
+    int j_stop = L - 1;       // the last sample the tile composites
 
     for (int j = 0; j < L; ++j) {
         const SamplePos cur = nxt;
@@ -492,9 +506,13 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
             // every later sample of this tile is exactly zero
             if (CKPT && rl.valid)
                 for (int c = j / K + 1; c * K < L; ++c) ckpt[(int64_t)c * R] = T;
+            j_stop = j;
             break;
         }
     }
+    // every lane stores the same value (no lane-divergent branch at the end of
+    // the persistent tile loop's body)
+    if (CKPT && P.tile_stop) P.tile_stop[STOP_HEAD + (int64_t)S.tile_off + tile] = j_stop;
 
     float ce = 0.0f, se = 0.0f;      // this lane's loss terms (LOSS)
     if (rl.valid) {
@@ -975,8 +993,19 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
     }
 
     int64_t st[6] = {0, 0, 0, 0, 0, 0};
+    // past the sample where the forward stopped this tile every ray is opaque
+    // or out of the grid: those samples add nothing
+    int stop = L - 1;
+    if (P.tile_stop) {
+        const int* h = P.tile_stop;
+        if (h[3] == 1 && h[0] == P.desc->tile_w && h[1] == L && h[2] == KC) {
+            const int v = h[STOP_HEAD + (int64_t)S.tile_off + tile];
+            stop = v < -1 ? -1 : v > L - 1 ? L - 1 : v;
+        }
+    }
     float Q = 0.0f;
     for (int ci = nck - 1; ci >= 0; --ci) {
+        if (ci * KC > stop) continue;
         const float Tc = rl.valid ? ckpt[(int64_t)ci * R + lane_lray(rl, S)] : 0.0f;
         if (wave_ballot((Tc > 0.0f) && (Tc >= kappa)) == 0) continue;
         const int j0 = ci * KC;
@@ -997,7 +1026,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         for (int jj = 0; jj < KC; ++jj) {
             pv[jj] = PV_DEAD;
             sx[jj] = sy[jj] = sz[jj] = 0.0f;
-            if (j0 + jj < L) {
+            if (j0 + jj <= stop) {
                 const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
                                                    rl.dx, rl.dy, rl.dz);
                 sx[jj] = sp.x; sy[jj] = sp.y; sz[jj] = sp.z;
@@ -1684,6 +1713,7 @@ static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, co
     P.gd_out = const_cast<float*>(io.g_depth); P.gs_out = const_cast<float*>(io.g_sem);
     P.lam_s = P.lam_d = 0.0f;
     P.lcount = l.lcount; P.lpart = l.lpart;
+    P.tile_stop = io.tile_stop;
     return P;
 }
 
@@ -1719,6 +1749,9 @@ static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
     prep_records<CP>(d, g, io, l, st);
     const int wpb = t.waves_per_block;
     Ctx P = P0;
+    if (P.tile_stop)
+        hipLaunchKernelGGL(k_stop_header, dim3(1), dim3(64), 0, st, P.tile_stop, d.tile_w, P.mr.L, P.mr.K,
+                           P.ckpt != nullptr && P.mr.K > 0 ? 1 : 0);
     // the union walk tests membership on packed cells
     if (!bitmap_fits(d.max_n, wpb) || !cells_fit(g)) P.bitmap_words = 0;
     const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);

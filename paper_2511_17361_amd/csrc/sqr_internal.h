@@ -72,6 +72,7 @@ struct BatchIO {
     const int32_t* sem_label;
     const float* depth_label;
     float* loss;
+    int32_t* tile_stop;       // nullable: [4 + total_tiles], header then one stop per tile
 };
 
 // Weights of the fused loss (Eq. eq:loss); nullptr = no loss epilogue.

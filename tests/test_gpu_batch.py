@@ -223,3 +223,37 @@ def test_bench_workload_step_gradients_on_sampled_rays():
     gref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d[ids], g_s[ids], index=index, ray_ids=ids)
     got = {k: out["g_" + k] for k in ("means", "quats", "scales", "eps", "opacity", "logits")}
     H.assert_grads_close(got, gref, "bench workload")
+
+
+def test_tile_stops_used_and_ignored():
+    """The forward records where each tile stopped; a backward with the same
+    tiling skips the samples past it, one with another tiling ignores the
+    record.  Both give the oracle's gradients, and the record's header names the
+    forward's tiling and march."""
+    scenes = _small_batch(seed=95, ns=(30, 12, 40), sizes=((24, 16), (9, 7), (16, 16)))
+    b = _make_batch(scenes)
+    ups = _upstream(scenes, 96)
+    for i, (gd, gs) in enumerate(ups):
+        b.set_upstream(i, torch.from_numpy(gd).cuda(), torch.from_numpy(gs).cuda())
+    b.build_index()
+    _say("tile stops: same tiling")
+    b.render_fwd(api.Tuning(8, 2, 0, 1, 4))
+    b.render_bwd(api.Tuning(8, 2, 2, 1, 4))
+    torch.cuda.synchronize()
+    head = b.buf["tile_stop"][:4].cpu().tolist()
+    assert head == [8, scenes[0].march.n_samples, 4, 1], head
+    L = scenes[0].march.n_samples
+    stops = b.buf["tile_stop"][4:].cpu().numpy()
+    assert np.any(stops < L - 1), "some tile must stop early (opaque or out of the grid)"
+    used = [{k: v.clone() for k, v in b.scene_outputs(i).items() if k.startswith("g_")} for i in range(3)]
+    _say("tile stops: other tiling")
+    b.render_fwd(api.Tuning(8, 2, 0, 1, 4))
+    b.render_bwd(api.Tuning(16, 2, 2, 1, 4))
+    torch.cuda.synchronize()
+    for i, sc in enumerate(scenes):
+        o = b.scene_outputs(i)
+        gd, gs = ups[i]
+        ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, gd, gs)
+        ign = {k[2:]: o[k].cpu().numpy() for k in o if k.startswith("g_")}
+        H.assert_grads_close({k[2:]: v.cpu().numpy() for k, v in used[i].items()}, ref, f"scene {i} stops used")
+        H.assert_grads_close(ign, ref, f"scene {i} stops ignored")
