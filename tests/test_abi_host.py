@@ -277,3 +277,26 @@ def test_march_kappa_outside_unit_interval_is_rejected(kappa):
     rc = lib.sq_render_fwd(ct.byref(_grid()), ct.byref(_index()), ct.byref(_prims()), ct.byref(_rays()), ct.byref(m),
                            FAKE, FAKE, None, FAKE, None, None, ct.byref(t), 0x100000, 1 << 30, None)
     assert rc == L.SQ_ERR_INVALID and "kappa" in lib.sq_last_error().decode()
+
+
+def test_tile_stop_length_query_and_short_buffer():
+    """4 + tiles of the call's tiling; a shorter buffer is refused before any
+    launch by the forwards and the backward."""
+    lib = L.load()
+    b = _batch()
+    # 3 scenes x 2 cameras of 13 x 9 pixels: 8 x 8 tiles 2 x 2, 16 x 4 tiles 1 x 3, 4 x 16 tiles 4 x 1
+    for tw, tiles in ((8, 24), (16, 18), (4, 24)):
+        t = L.SqTuning(tw, 4, 0, 0, 4)
+        assert lib.sq_batch_tile_stop_len(ct.byref(b), ct.byref(t)) == 4 + tiles
+    assert lib.sq_batch_tile_stop_len(ct.byref(b), ct.byref(L.SqTuning(5, 4, 0, 0, 4))) == 0
+    io = _batch_io()
+    io.tile_stop_len = 4 + 24 - 1
+    t = L.SqTuning(8, 4, 0, 0, 4)
+    assert lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30,
+                                   None) == L.SQ_ERR_CAPACITY
+    assert "tile_stop" in lib.sq_last_error().decode()
+    assert lib.sq_batch_render_bwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30,
+                                   None) == L.SQ_ERR_CAPACITY
+    w = L.SqLossWeights(2.0, 0.05)
+    assert lib.sq_batch_render_fwd_loss(ct.byref(b), ct.byref(io), ct.byref(w), ct.byref(t), 0x100000, 1 << 30,
+                                        None) == L.SQ_ERR_CAPACITY
