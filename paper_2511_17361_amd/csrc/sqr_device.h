@@ -29,7 +29,6 @@ namespace sqr {
 constexpr int REC = 28;
 constexpr int EMPTY_BOX = 0x7fff7fff;
 constexpr float F_CULL = 110.0f;          // exp(-110) = 1.7e-48: 0 in float32
-constexpr float LOG2E = 1.4426950408889634f;
 constexpr float LN2 = 0.6931471805599453f;
 
 // Read-only views in the constant address space.  The kernels store floats
@@ -169,9 +168,9 @@ constexpr float L2_LOG2E = 0.5287663729448977f;
 
 // Evaluation for the adjoint.  B and Z are carried divided by ln 2 (one FMA
 // each instead of a multiply), so p = 2^-(Bs + Zs) needs no extra scaling;
-// the adjoint's per-primitive factors absorb the ln 2.  p may differ from
-// eval_p's in the last bit.  Returns false when the pair is culled (float32
-// exp(-f) would be exactly 0).
+// the adjoint's per-primitive factors absorb the ln 2.  p is computed by the
+// same operations as in eval_p, so both give the same bits.  Returns false
+// when the pair is culled (float32 exp(-f) would be exactly 0).
 template <typename RecT>
 __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, float z,
                                           float dxyz[3], PairEval& e) {
@@ -206,7 +205,8 @@ __device__ __forceinline__ bool pair_kept(cf_ptr rec, float x, float y, float z)
     return fmaxf(fmaxf(fabsf(u), fabsf(v)), fabsf(w)) < rec[16];
 }
 
-// Forward-only evaluation: returns p (0 when culled).
+// Evaluation of p alone (0 when culled), by eval_pair's operations: B and Z
+// divided by ln 2 through the exponent, so p = 2^-(Bs + Zs) takes no multiply.
 template <typename RecT>
 __device__ __forceinline__ float eval_p(const RecT& rec, float x, float y, float z) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
@@ -220,9 +220,9 @@ __device__ __forceinline__ float eval_p(const RecT& rec, float x, float y, float
         const float a = rec[12], b = rec[13], ee = rec[14];
         const float X = hw_exp2(a * hw_log2(au));
         const float Y = hw_exp2(a * hw_log2(av));
-        const float Z = hw_exp2(b * hw_log2(aw));
-        const float B = hw_exp2(ee * hw_log2(X + Y));
-        p = hw_exp2(-LOG2E * (B + Z));
+        const float Zs = hw_exp2(fmaf(b, hw_log2(aw), L2_LOG2E));
+        const float Bs = hw_exp2(fmaf(ee, hw_log2(X + Y), L2_LOG2E));
+        p = hw_exp2(-(Bs + Zs));
     }
     return p;
 }
