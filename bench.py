@@ -211,7 +211,7 @@ def batched_8_scenes(dev, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 (sharding over several GPUs is a design, not code)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -383,7 +383,7 @@ def main():
     torch.cuda.synchronize()
     t_vox = ve[0].elapsed_time(ve[1]) / args.steps
 
-    workload = (f"config {args.config}: {len(scenes)} scene(s), {sum(s.prims.n for s in scenes)} superquadrics "
+    workload = (f"{len(scenes)} scene(s), {sum(s.prims.n for s in scenes)} superquadrics "
                 f"({'/'.join(str(s.prims.n) for s in scenes)}), {sc0.rays.shape[0]} cameras x "
                 f"{sc0.rays.shape[2]}x{sc0.rays.shape[1]} rays per scene, L={Ls} in [{sc0.march.t_near}, "
                 f"{sc0.march.t_far}] m, C={C}, grid {'x'.join(map(str, sc0.grid.dims))} at {sc0.grid.voxel} m, "

@@ -39,7 +39,7 @@ typedef int32_t sq_status;
 #define SQ_ERR_INVALID    -1  /* bad argument (detected on the host, nothing launched) */
 #define SQ_ERR_CAPACITY   -2  /* workspace or index capacity too small (host-detectable) */
 #define SQ_ERR_HIP        -3  /* a HIP runtime call failed; see sq_last_error() */
-#define SQ_ERR_UNSUPPORTED -4 /* valid request this build does not implement */
+#define SQ_ERR_UNSUPPORTED -4 /* valid request that this library does not implement */
 
 #define SQ_MAX_CLASSES 32     /* largest supported number of semantic classes C */
 

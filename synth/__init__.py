@@ -165,7 +165,7 @@ def _ground_heavy_centres(rng, n):
 
 
 def config(cfg: int, scene: int = 0, n_prims: int | None = None) -> Scene:
-    """The five workloads of the build.
+    """Five seeded workloads, numbered 0..4:
 
     0: tiny 16x16x4 grid at 0.5 m, 64 SQs, 1 camera 64x48, L=32 to 12 m, C=4.
     1: Occ3D-shaped grid, 6,400 SQs, 6 cameras 352x200, L=100 to 45 m, C=17.

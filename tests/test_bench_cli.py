@@ -1,6 +1,6 @@
 """bench.py's command line, on the CPU: the options parse, and a request for
-more than one GPU ends with a message and a non-zero status (this build runs
-on one GPU)."""
+more than one GPU ends with a message and a non-zero status (the bench
+measures one GPU)."""
 import json
 import os
 import subprocess
