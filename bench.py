@@ -208,6 +208,47 @@ def batched_8_scenes(dev, steps, warmup):
                             persistent=tune.persistent, chunk=tune.chunk))
 
 
+def paper_setting(dev, steps):
+    """The paper's render setting: 6 cameras x 704x256 rays, 1,600 superquadrics,
+    L = 100 in [0.1, 40] m, N_v = 5.  Timed: the index build and the plain
+    forward (depth, semantics and probabilities, no checkpoints), the render the
+    paper times per frame of six views in Table tab:ablation_render_occ.  The
+    primitives are synthetic, so the paper's figure is context only."""
+    import torch
+
+    import synth
+    from paper_2511_17361_amd import api
+    sc = synth.paper_render_scene()
+    grid, march = api.Grid.of(sc.grid), api.March.of(sc.march)
+    prims, rays = api.Prims.from_numpy(sc.prims, dev), api.Rays.from_numpy(sc.rays, dev)
+    wi, wf = api.Workspace(dev), api.Workspace(dev)
+    idx = api.build_index(grid, prims, ws=wi)
+    out = api.render_fwd(grid, idx, prims, rays, march, ws=wf)
+    torch.cuda.synchronize()
+    E = idx.checked_total()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(steps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    t_idx = timed(lambda: api.build_index(grid, prims, ws=wi, out=idx))
+    t_fwd = timed(lambda: api.render_fwd(grid, idx, prims, rays, march, ws=wf, out=out))
+    R = sc.rays.n_rays
+    return dict(workload=("6 cameras x 704x256 rays, 1600 superquadrics, L=100 in [0.1, 40] m, N_v=5, C=17, "
+                          "grid 200x200x16 at 0.4 m; synthetic primitives; index + plain forward"),
+                index_entries=E, index_ms=t_idx, fwd_ms=t_fwd, render_ms=t_idx + t_fwd,
+                ray_samples_per_s=R * sc.march.n_samples / ((t_idx + t_fwd) / 1e3),
+                paper=dict(render_ms=17.2, hardware="1x NVIDIA A100",
+                           source="Table tab:ablation_render_occ, six views, trained primitives"))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -451,6 +492,7 @@ def main():
 
     result["sq_major_ab"] = sq_major_ab(dev, args.steps)
     result["batched_8_scenes"] = batched_8_scenes(dev, args.steps, args.warmup)
+    result["paper_setting"] = paper_setting(dev, args.steps)
 
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4

@@ -222,6 +222,21 @@ def config(cfg: int, scene: int = 0, n_prims: int | None = None) -> Scene:
     return Scene(grid, prims, rays, march, name=f"cfg{cfg}_s{scene}")
 
 
+def paper_render_scene(seed: int = 0) -> Scene:
+    """The render setting of the paper's implementation details (Sec. 4,
+    "Implementation Details"), whose render time Table tab:ablation_render_occ
+    reports: 6 surround cameras at 704x256, N = 1,600 superquadrics, N_v = 5,
+    L = 100 samples in [0.1, 40] m without early termination, on the Occ3D
+    grid (200x200x16 at 0.4 m), C = 17.  The primitives are drawn like those of
+    workloads 1-3 (ground-heavy centres, scales 0.2-3 m), not trained ones; the
+    cameras have a 70 degree horizontal field of view, 60 degrees apart."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 900 + seed))
+    grid = Grid(**OCC3D_GRID, nv=5)
+    prims = make_prims(rng, _ground_heavy_centres(rng, 1600), 0.2, 3.0, 17)
+    rays = pinhole_rig(6, 704, 256, 70.0, (0.0, 0.0, 1.5))
+    return Scene(grid, prims, rays, March(100, 0.1, 40.0), name=f"paper_render_s{seed}")
+
+
 def upstream_grads(rng, rays: Rays, n_classes: int):
     """g_D ~ N(0,1) per pixel, g_S ~ N(0,1) per pixel and class; layouts
     [cams,H,W] and [cams,C,H,W]."""
