@@ -156,6 +156,15 @@ def test_fwd_config4_sampled_rays():
     _fwd_case(sc, ray_ids=ids, what="cfg4")
 
 
+def test_fwd_paper_render_setting_sampled_rays():
+    """The paper's render setting that the bench times beside its figure
+    (6 x 704x256 rays, 1,600 superquadrics, L = 100 in [0.1, 40] m)."""
+    sc = synth.paper_render_scene()
+    ids = np.random.default_rng(2).choice(sc.rays.n_rays, 2000, replace=False)
+    _say("fwd paper render setting")
+    _fwd_case(sc, ray_ids=ids, what="paper setting")
+
+
 def test_fwd_bitmap_union_walk_equals_voxel_group_walk():
     """140k primitives: with one wave per block the per-wave union bitmap fits
     the LDS budget, with four it does not and mixed-voxel samples walk one
