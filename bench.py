@@ -95,7 +95,8 @@ def parse():
     ap.add_argument("--tile-w", type=int, default=8)
     ap.add_argument("--wpb", type=int, default=2)
     ap.add_argument("--bwd-mode", type=int, default=0, help="0 auto, 1 sample-major, 2 primitive-major")
-    ap.add_argument("--cpu-rays", type=int, default=32768, help="rays in the oracle's CPU sample")
+    ap.add_argument("--cpu-rays", type=int, default=6 * 8192, help="rays in the oracle's CPU sample")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="CPU-baseline worker processes (0: every core, <= 16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--autotune", action="store_true",
@@ -105,25 +106,72 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(sc, n_rays, seed=0):
+_CPU = {}
+
+
+def _cpu_tile(span):
+    """One worker's share of the CPU baseline: the oracle's forward and adjoint
+    over rays [s, e) of the seeded sample (one NumPy thread per process)."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    s, e = span
+    c = _CPU
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.render(c["sc"].grid, c["sc"].prims, c["sc"].rays, c["sc"].march, index=c["index"],
+                      ray_ids=c["ids"][s:e])
+        oracle.render_grad(c["sc"].grid, c["sc"].prims, c["sc"].rays, c["sc"].march, c["gd"][s:e], c["gs"][s:e],
+                           index=c["index"], ray_ids=c["ids"][s:e])
+    return time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_procs_default():
+    """Worker processes of the CPU baseline: every core this process may run
+    on, at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(sc, n_rays, procs, seed=0, tile=512):
     """The FP64 oracle (forward + adjoint) on a seeded ray sample of the same
-    workload, single process."""
+    workload, split into tiles of `tile` rays over `procs` forked worker
+    processes.  Runs before anything initialises the GPU (the workers are
+    forks of this process).  The index is built once, untimed, and shared."""
+    import multiprocessing as mp
+
     import numpy as np
     import oracle
     rng = np.random.default_rng(seed)
     ids = np.sort(rng.choice(sc.rays.n_rays, n_rays, replace=False))
     C = sc.prims.n_classes
-    g_d = rng.standard_normal(n_rays)
-    g_s = rng.standard_normal((n_rays, C))
-    index = oracle.build_index(sc.prims.means, sc.grid)[:3]      # untimed: the index is shared
-    t0 = time.perf_counter()
-    oracle.render(sc.grid, sc.prims, sc.rays, sc.march, index=index, ray_ids=ids)
-    oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s, index=index, ray_ids=ids)
-    dt = time.perf_counter() - t0
-    rs = n_rays * sc.march.n_samples / dt
-    return dict(value=rs, unit="ray-samples/s", cores=1, kind="oracle",
-                sample=f"{n_rays} seeded rays of the same workload, forward + adjoint, FP64 NumPy, "
-                       f"one process ({dt:.1f} s); index build excluded")
+    _CPU.update(sc=sc, ids=ids, gd=rng.standard_normal(n_rays), gs=rng.standard_normal((n_rays, C)),
+                index=oracle.build_index(sc.prims, sc.grid)[:3])
+    spans = [(s, min(n_rays, s + tile)) for s in range(0, n_rays, tile)]
+    with mp.get_context("fork").Pool(procs) as pool:
+        t0 = time.perf_counter()
+        busy = pool.map(_cpu_tile, spans, chunksize=1)
+        wall = time.perf_counter() - t0
+    _CPU.clear()
+    rs = n_rays * sc.march.n_samples / wall
+    return dict(value=rs, unit="ray-samples/s", cores=procs, kind="oracle",
+                cpu_model=_cpu_model(), os_cpu_count=os.cpu_count(),
+                sample=(f"{n_rays} seeded rays of the same workload (a subset: {n_rays / sc.rays.n_rays:.2%} of its "
+                        f"rays), forward + adjoint, FP64 NumPy, {len(spans)} tiles of {tile} rays over {procs} "
+                        f"processes ({wall:.1f} s wall, {sum(busy):.1f} s of worker time); index build excluded"))
 
 
 def sq_major_ab(dev, steps, K=4):
@@ -255,15 +303,21 @@ def main():
         print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 (sharding over several GPUs is a design, not code)"}))
         sys.exit(2)
     import numpy as np
-    import torch
 
     import synth
+    scenes = [synth.config(3, s) for s in range(8)] if args.config == 3 else [synth.config(args.config)]
+    sc0 = scenes[0]
+    # the CPU baseline forks its workers before anything touches the GPU
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(sc0, args.cpu_rays, args.cpu_procs or cpu_procs_default())
+
+    import torch
+
     from paper_2511_17361_amd import api
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
-    scenes = [synth.config(3, s) for s in range(8)] if args.config == 3 else [synth.config(args.config)]
-    sc0 = scenes[0]
     grid = api.Grid.of(sc0.grid)
     march = api.March(sc0.march.n_samples, sc0.march.t_near, sc0.march.t_far, args.ckpt_every)
     C = sc0.prims.n_classes
@@ -503,8 +557,8 @@ def main():
         torch.cuda.synchronize()
         result["calib_copy_bytes"] = 4 * n
 
-    if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(sc0, args.cpu_rays)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
 
 

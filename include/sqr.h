@@ -365,9 +365,18 @@ typedef struct {
      * when the header does not match its own tiling and march it ignores the
      * buffer.  Like the checkpoints, the buffer belongs to the last forward:
      * pass it to both calls or to neither.  tile_stop holds tile_stop_len
-     * int32, at least sq_batch_tile_stop_len(); shorter: SQ_ERR_CAPACITY. */
+     * int32, at least sq_batch_tile_stop_len(); shorter: SQ_ERR_CAPACITY.
+     * A backward whose chunk K or sample count L differs from the ones the
+     * header records for a forward with checkpoints (the checkpoint rows are
+     * laid out by that forward's K) cannot detect the mismatch on the host;
+     * it writes NaN to every gradient output instead of gradients read from
+     * wrongly laid-out checkpoints. */
     int32_t *tile_stop;
     int64_t  tile_stop_len;
+    /* Floats that io->ckpt holds.  A call that reads or writes checkpoints
+     * with chunk K needs ceil(L/K) * (sum of rays) of them; fewer:
+     * SQ_ERR_CAPACITY, nothing launched. */
+    int64_t  ckpt_len;
 } sq_batch_io;
 
 /* Bytes of workspace every batched call needs (host-only; 0 on bad input). */
@@ -384,8 +393,9 @@ sq_status sq_batch_build_index(const sq_batch* batch, const sq_batch_io* io,
                                void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* sq_render_fwd for every scene of the batch in one launch (Sec. 3.3
- * "Forward Pass"); checkpoints are written when io->ckpt is not NULL.
- * `stats` as for sq_render_fwd. */
+ * "Forward Pass"); checkpoints are written when io->ckpt is not NULL, which
+ * needs a chunk in {4, 8, 16} (the backward's) and io->ckpt_len floats for
+ * it.  `stats` as for sq_render_fwd. */
 sq_status sq_batch_render_fwd(const sq_batch* batch, const sq_batch_io* io, int64_t* stats,
                               const sq_tuning* tuning, void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -435,8 +445,8 @@ sq_status sq_graph_destroy(sq_graph graph);
  * timed steps, HIP events on `stream`) and returns the fastest in
  * *best_index and each candidate's mean step time in ms_per_candidate
  * (nullable, n_candidates floats).  SYNCHRONOUS: waits for the stream.  All
- * candidates are validated before the first launch.  The ckpt buffer must
- * hold ceil(L/K) * sum rays floats for the smallest chunk K among them. */
+ * candidates are validated before the first launch, io->ckpt_len included
+ * (ceil(L/K) * sum rays floats for every candidate's chunk K). */
 sq_status sq_batch_autotune(const sq_batch* batch, const sq_batch_io* io, const sq_tuning* candidates,
                             int32_t n_candidates, int32_t reps, int32_t* best_index, float* ms_per_candidate,
                             void* ws, size_t ws_bytes, hipStream_t stream);

@@ -64,7 +64,7 @@ import numpy as np
 __all__ = [
     "pinned_inv_voxel", "sample_depths", "voxel_of_points", "centre_boxes", "influence_boxes",
     "build_index", "rotation_matrix", "inside_outside", "occupancy",
-    "render", "render_grad", "box_volume_total",
+    "render", "render_grad", "box_volume_total", "pair_records",
 ]
 
 F32 = np.float32
@@ -371,6 +371,24 @@ def _march(grid, prims, rays_o, rays_d, march, index, brute, P, want_pairs):
     if kappa > 0:
         margin = np.minimum(margin, np.abs(T / kappa - 1.0))
     return depth, sem, T, records, margin
+
+
+def pair_records(grid, prims, rays, march, index=None, ray_ids=None):
+    """Per-sample records of the front-to-back march ("Forward Pass"), for
+    counting the method's units: one dict per sample index j with the FP32
+    depth t, every ray's a_j and T_j, and the listed pairs of that sample as
+    (r = ray index within the batch, k = primitive id, x = the pinned FP32
+    sample point as FP64).  A sample contributes pairs only when its ray is
+    still marching (T_j > 0, T_j >= kappa), its point lies in the grid and
+    its voxel lists at least one primitive."""
+    if index is None:
+        index = build_index(prims, grid)[:3]
+    P = _Prep(prims)
+    o = rays.origins.reshape(-1, 3)
+    d = rays.dirs.reshape(-1, 3)
+    if ray_ids is not None:
+        o, d = o[ray_ids], d[ray_ids]
+    return _march(grid, prims, o, d, march, index, False, P, True)[3]
 
 
 def _softmax(z):

@@ -89,7 +89,7 @@ class SqBatchIO(ct.Structure):
         "counts", "offsets", "ids", "totals", "depth", "sem", "probs", "t_final", "ckpt",
         "g_depth", "g_sem", "g_means", "g_quats", "g_scales", "g_eps", "g_opacity", "g_logits",
         "vox_density", "vox_sem", "vox_labels", "sem_label", "depth_label", "loss", "tile_stop")] + [
-        ("tile_stop_len", ct.c_int64)]
+        ("tile_stop_len", ct.c_int64), ("ckpt_len", ct.c_int64)]
 
 
 class SqLossWeights(ct.Structure):

@@ -491,6 +491,8 @@ class Batch:
             setattr(io, name, _ptr(vals.get(name)))
         if vals.get("tile_stop") is not None:
             io.tile_stop_len = int(vals["tile_stop"].numel())
+        if vals.get("ckpt") is not None:
+            io.ckpt_len = int(vals["ckpt"].numel())
         return io
 
     def _call(self, fn, *args):

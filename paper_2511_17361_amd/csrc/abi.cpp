@@ -4,6 +4,7 @@
 // batch of one.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -114,6 +115,16 @@ sq_status tuning_of(const sq_tuning* t, sqr::TuneDev& d) {
     return SQ_OK;
 }
 
+// Upper bound of E for n primitives: n * prod_axis min(2 nv + 1, dims).
+int64_t index_bound(const sq_grid* g, int32_t n) {
+    int64_t per = 1;
+    for (int i = 0; i < 3; ++i) {
+        const int64_t side = 2 * (int64_t)g->nv + 1;
+        per *= side < g->dims[i] ? side : g->dims[i];
+    }
+    return per * n;
+}
+
 // A validated batch: host description plus the per-call constants.
 struct Plan {
     sqr::GridDev g;
@@ -139,6 +150,16 @@ sq_status make_plan(const sq_batch* b, int tile_w, Plan& p) {
         if (sc.n_prims < 0 || sc.n_cams < 0 || sc.height < 0 || sc.width < 0)
             return fail(SQ_ERR_INVALID, "scene %d: negative size", i);
         if (sc.index_capacity < 0) return fail(SQ_ERR_INVALID, "scene %d: index_capacity < 0", i);
+        // V_f holds int32 offsets into the scene's ids: every entry the index
+        // can hold (the capacity) and every entry it can need (the box bound)
+        // must stay addressable by them
+        if (sc.index_capacity > INT32_MAX)
+            return fail(SQ_ERR_UNSUPPORTED, "scene %d: index_capacity %lld exceeds the int32 offsets of V_f", i,
+                        (long long)sc.index_capacity);
+        if (index_bound(&b->grid, sc.n_prims) > INT32_MAX)
+            return fail(SQ_ERR_UNSUPPORTED,
+                        "scene %d: %d primitives can need %lld index entries, beyond the int32 offsets of V_f", i,
+                        sc.n_prims, (long long)index_bound(&b->grid, sc.n_prims));
         prims += sc.n_prims;
         rays += (int64_t)sc.n_cams * sc.height * sc.width;
         if (prims >= ((int64_t)1 << 30)) return fail(SQ_ERR_INVALID, "too many primitives");
@@ -224,6 +245,20 @@ sq_status check_tile_stop(const Plan& p, const sq_batch_io* io) {
     return SQ_OK;
 }
 
+// The checkpoints of a chunk K: ceil(L/K) rows of every ray of the batch must
+// fit the caller's ckpt_len floats.
+sq_status check_ckpt(const Plan& p, const sq_batch_io* io, int K) {
+    if (!io->ckpt) return SQ_OK;
+    if (K < 1) return fail(SQ_ERR_INVALID, "ckpt given but the checkpoint spacing is < 1");
+    const int64_t need = (int64_t)((p.m.n_samples + K - 1) / K) * p.d.total_rays;
+    if (io->ckpt_len < need)
+        return fail(SQ_ERR_CAPACITY, "ckpt_len %lld < %lld floats for chunk %d", (long long)io->ckpt_len,
+                    (long long)need, K);
+    return SQ_OK;
+}
+
+bool chunk_ok(int K) { return K == 4 || K == 8 || K == 16; }
+
 sq_status fwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, const sq_tuning* tuning, void* ws,
                       size_t ws_bytes, hipStream_t stream) {
     sq_status s;
@@ -231,7 +266,7 @@ sq_status fwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
     if (p.d.total_rays > 0 && (!io->depth || !io->sem || !io->t_final))
         return fail(SQ_ERR_INVALID, "depth/sem/t_final is NULL");
     const int K = chunk_of(tuning, p.m);
-    if (io->ckpt && K < 1) return fail(SQ_ERR_INVALID, "ckpt given but the checkpoint spacing is < 1");
+    if ((s = check_ckpt(p, io, K))) return s;
     if ((s = check_tile_stop(p, io))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
@@ -246,9 +281,10 @@ sq_status bwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
     sq_status s;
     if ((s = check_io_render(p, io))) return s;
     const int K = chunk_of(tuning, p.m);
-    if (!(K == 4 || K == 8 || K == 16))
+    if (!chunk_ok(K))
         return fail(SQ_ERR_INVALID, "backward needs a checkpoint spacing in {4, 8, 16} (got %d)", K);
     if (p.d.total_rays > 0 && !io->ckpt) return fail(SQ_ERR_INVALID, "ckpt is NULL");
+    if ((s = check_ckpt(p, io, K))) return s;
     if (p.d.total_prims > 0 && (!io->g_means || !io->g_quats || !io->g_scales || !io->g_eps || !io->g_opacity ||
                                 !io->g_logits))
         return fail(SQ_ERR_INVALID, "a gradient output array is NULL");
@@ -284,7 +320,7 @@ sq_status fwd_loss_checked(const Plan& p, const sq_batch_io* io, const sq_loss_w
         return fail(SQ_ERR_INVALID, "depth/sem/t_final is NULL");
     if ((s = check_loss(p, io, w))) return s;
     const int K = chunk_of(tuning, p.m);
-    if (io->ckpt && K < 1) return fail(SQ_ERR_INVALID, "ckpt given but the checkpoint spacing is < 1");
+    if ((s = check_ckpt(p, io, K))) return s;
     if ((s = check_tile_stop(p, io))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
@@ -360,6 +396,11 @@ void io_from(const sq_index* idx, const sq_prims* pr, const sq_rays* rays, sq_ba
     io.counts = idx->counts; io.offsets = idx->offsets; io.ids = idx->ids; io.totals = idx->total;
 }
 
+// Rows of the single-scene checkpoint layout [ceil(L/K), R] (0 without checkpoints).
+int64_t ckpt_rows(const sq_march* m) {
+    return m->ckpt_every > 0 ? (m->n_samples + m->ckpt_every - 1) / m->ckpt_every : 0;
+}
+
 struct GraphImpl {
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -373,18 +414,13 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 206; }
+int32_t sq_version(void) { return 207; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
 int64_t sq_index_capacity_bound(const sq_grid* grid, int32_t n) {
     if (!grid_ok(grid) || n < 0) return -1;
-    int64_t per = 1;
-    for (int i = 0; i < 3; ++i) {
-        const int64_t side = 2 * (int64_t)grid->nv + 1;
-        per *= side < grid->dims[i] ? side : grid->dims[i];
-    }
-    return per * n;
+    return index_bound(grid, n);
 }
 
 size_t sq_build_index_workspace(const sq_grid* grid, int32_t n) {
@@ -442,6 +478,7 @@ sq_status sq_render_fwd(const sq_grid* grid, const sq_index* idx, const sq_prims
     sq_batch_io io;
     io_from(idx, prims, rays, io);
     io.depth = depth; io.sem = sem; io.probs = probs; io.t_final = t_final; io.ckpt = ckpt;
+    io.ckpt_len = ckpt_rows(march) * p.d.total_rays;     // [ceil(L/K), R] by this call's contract
     sq_tuning t = tuning ? *tuning : default_tuning();
     t.chunk = march->ckpt_every;
     return fwd_checked(p, &io, stats, &t, ws, ws_bytes, stream);
@@ -471,6 +508,7 @@ sq_status sq_render_bwd(const sq_grid* grid, const sq_index* idx, const sq_prims
     sq_batch_io io;
     io_from(idx, prims, rays, io);
     io.ckpt = const_cast<float*>(ckpt);
+    io.ckpt_len = ckpt_rows(march) * p.d.total_rays;
     io.g_depth = g_depth; io.g_sem = g_sem;
     io.g_means = grads->means; io.g_quats = grads->quats; io.g_scales = grads->scales; io.g_eps = grads->eps;
     io.g_opacity = grads->opacity; io.g_logits = grads->logits;
@@ -500,6 +538,7 @@ sq_status sq_render_fwd_loss(const sq_grid* grid, const sq_index* idx, const sq_
     sq_batch_io io;
     io_from(idx, prims, rays, io);
     io.depth = depth; io.sem = sem; io.probs = probs; io.t_final = t_final; io.ckpt = ckpt;
+    io.ckpt_len = ckpt_rows(march) * p.d.total_rays;
     io.sem_label = sem_label; io.depth_label = depth_label; io.g_depth = g_depth; io.g_sem = g_sem; io.loss = loss;
     sq_tuning t = tuning ? *tuning : default_tuning();
     t.chunk = march->ckpt_every;
@@ -547,6 +586,7 @@ sq_status sq_render_bwd_sq_major(const sq_grid* grid, const sq_index* idx, const
     sq_batch_io io;
     io_from(idx, prims, rays, io);
     io.ckpt = const_cast<float*>(ckpt);
+    io.ckpt_len = ckpt_rows(march) * p.d.total_rays;
     io.g_depth = g_depth; io.g_sem = g_sem;
     io.g_means = grads->means; io.g_quats = grads->quats; io.g_scales = grads->scales; io.g_eps = grads->eps;
     io.g_opacity = grads->opacity; io.g_logits = grads->logits;
@@ -613,6 +653,8 @@ sq_status sq_batch_render_fwd(const sq_batch* b, const sq_batch_io* io, int64_t*
     if ((s = tuning_of(tuning, tune))) return s;
     Plan p;
     if ((s = make_plan(b, tune.tile_w, p))) return s;
+    if (io && io->ckpt && !chunk_ok(chunk_of(tuning, p.m)))
+        return fail(SQ_ERR_INVALID, "checkpoints need a chunk in {4, 8, 16} (got %d)", chunk_of(tuning, p.m));
     return fwd_checked(p, io, stats, tuning, ws, ws_bytes, stream);
 }
 
@@ -623,6 +665,8 @@ sq_status sq_batch_render_fwd_loss(const sq_batch* b, const sq_batch_io* io, con
     if ((s = tuning_of(tuning, tune))) return s;
     Plan p;
     if ((s = make_plan(b, tune.tile_w, p))) return s;
+    if (io && io->ckpt && !chunk_ok(chunk_of(tuning, p.m)))
+        return fail(SQ_ERR_INVALID, "checkpoints need a chunk in {4, 8, 16} (got %d)", chunk_of(tuning, p.m));
     return fwd_loss_checked(p, io, weights, tuning, ws, ws_bytes, stream);
 }
 
@@ -663,7 +707,9 @@ sq_status check_step(const sq_batch* b, const sq_batch_io* io, const sq_tuning* 
         return fail(SQ_ERR_INVALID, "a step needs totals, forward outputs, ckpt and gradient outputs");
     if (w && (s = check_loss(p, io, w))) return s;
     const int K = chunk_of(tuning, p.m);
-    if (!(K == 4 || K == 8 || K == 16)) return fail(SQ_ERR_INVALID, "step needs a chunk in {4, 8, 16}");
+    if (!chunk_ok(K)) return fail(SQ_ERR_INVALID, "step needs a chunk in {4, 8, 16}");
+    if ((s = check_ckpt(p, io, K))) return s;
+    if ((s = check_tile_stop(p, io))) return s;
     if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
         !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
         return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply");
@@ -767,7 +813,10 @@ sq_status sq_batch_autotune(const sq_batch* b, const sq_batch_io* io, const sq_t
         if ((s = check_io_render(p, io))) return s;
         if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
         const int K = chunk_of(&candidates[i], p.m);
-        if (!(K == 4 || K == 8 || K == 16)) return fail(SQ_ERR_INVALID, "candidate %d: chunk %d", i, K);
+        if (!chunk_ok(K)) return fail(SQ_ERR_INVALID, "candidate %d: chunk %d", i, K);
+        if (!io->ckpt) return fail(SQ_ERR_INVALID, "autotune times full steps: ckpt is NULL");
+        if ((s = check_ckpt(p, io, K))) return s;
+        if ((s = check_tile_stop(p, io))) return s;
         if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
             !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
             return fail(SQ_ERR_UNSUPPORTED, "candidate %d: primitive-major backward does not apply", i);

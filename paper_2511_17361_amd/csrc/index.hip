@@ -114,7 +114,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_tile_lists(const BatchDesc* __
                     const int4 cb = cand[c];
                     if (box_has(cb.y, ix) & box_has(cb.z, iy) & box_has(cb.w, iz)) {
                         if (WRITE) {
-                            if (cursor < capacity) ids[cursor] = cb.x;
+                            // (the host keeps every offset within int32 and the
+                            // capacity; the guard holds whatever offsets hold)
+                            if (cursor >= 0 && cursor < capacity) ids[cursor] = cb.x;
                             ++cursor;
                         } else {
                             ++cnt;

@@ -1522,15 +1522,28 @@ __global__ __launch_bounds__(256) void k_sqm_reduce(Ctx P, const float* __restri
 //   g_m = -R^T sum(g_xs);  g_s_i = -(1/s_i) [G_R R^T]_ii  (G_R = sum g_xs (x-m)^T)
 //   g_q = (I - q^ q^T)/|q| * sum_ij G_R_ij dR_ij/dq^
 // ---------------------------------------------------------------------------
+// With `stop` (the forward's tile-stop record, nullable): when that record
+// says a forward with checkpoints ran with another sample count or chunk than
+// this backward's (L, K), the checkpoint rows were laid out for the other
+// chunk and every gradient written is NaN.
 template <int CP>
 __global__ __launch_bounds__(256) void k_finalize(int n_total, int C, const float* __restrict__ quats,
                                                   const float* __restrict__ scales, const float* __restrict__ rec,
                                                   const float* __restrict__ acc, float* g_means, float* g_quats,
                                                   float* g_scales, float* g_eps, float* g_opacity,
-                                                  float* g_logits) {
+                                                  float* g_logits, const int* __restrict__ stop, int L, int K) {
     constexpr int VP = AccRow<CP>::P;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_total) return;
+    if (stop && stop[3] == 1 && (stop[1] != L || stop[2] != K)) {
+        const float nan = __int_as_float(0x7fc00000);
+        for (int i = 0; i < 3; ++i) { g_means[3 * k + i] = nan; g_scales[3 * k + i] = nan; }
+        for (int i = 0; i < 4; ++i) g_quats[4 * k + i] = nan;
+        g_eps[2 * k] = g_eps[2 * k + 1] = nan;
+        g_opacity[k] = nan;
+        for (int c = 0; c < C; ++c) g_logits[(size_t)k * C + c] = nan;
+        return;
+    }
     // the accumulated sums carry no per-primitive constant factors (pair_adjoint)
     const cf_ptr r = as_const(rec) + (size_t)k * REC;
     float a[A_LG];
@@ -1903,7 +1916,7 @@ static void sqm_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
                            (const uint32_t*)q.pairs, capacity);                                      // Process 3
         hipLaunchKernelGGL(k_finalize<CP>, dim3((n + 255) / 256), dim3(256), 0, st, n, d.C, io.quats, io.scales,
                            (const float*)l.rec, (const float*)l.acc, io.g_means, io.g_quats, io.g_scales,
-                           io.g_eps, io.g_opacity, io.g_logits);
+                           io.g_eps, io.g_opacity, io.g_logits, (const int*)nullptr, P.mr.L, P.mr.K);
     }
 }
 
@@ -1969,7 +1982,8 @@ static void bwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
     if (d.total_prims > 0)
         hipLaunchKernelGGL(k_finalize<CP>, dim3((d.total_prims + 255) / 256), dim3(256), 0, st, d.total_prims, d.C,
                            io.quats, io.scales, (const float*)l.rec, (const float*)l.acc, io.g_means,
-                           io.g_quats, io.g_scales, io.g_eps, io.g_opacity, io.g_logits);
+                           io.g_quats, io.g_scales, io.g_eps, io.g_opacity, io.g_logits,
+                           (const int*)io.tile_stop, P.mr.L, P.mr.K);
 }
 
 hipError_t launch_batch_bwd(const GridDev& g, const BatchDesc& d, const MarchDev& mr, const BatchIO& io,

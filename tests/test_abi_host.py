@@ -218,6 +218,8 @@ def _batch_io():
     io = L.SqBatchIO()
     for name, _ in L.SqBatchIO._fields_:
         setattr(io, name, FAKE)
+    io.tile_stop_len = 1 << 40
+    io.ckpt_len = 1 << 40
     return io
 
 
@@ -300,3 +302,69 @@ def test_tile_stop_length_query_and_short_buffer():
     w = L.SqLossWeights(2.0, 0.05)
     assert lib.sq_batch_render_fwd_loss(ct.byref(b), ct.byref(io), ct.byref(w), ct.byref(t), 0x100000, 1 << 30,
                                         None) == L.SQ_ERR_CAPACITY
+
+
+def test_index_offsets_must_fit_int32():
+    """V_f holds int32 offsets: a scene whose capacity, or whose worst-case
+    entry count n * prod(min(2 N_v + 1, dims)), exceeds 2^31 - 1 is refused
+    before any launch (index build, renders, steps)."""
+    lib = L.load()
+    INT32_MAX = 2 ** 31 - 1
+    g = _grid()                                   # 11^3 = 1331 cells per primitive at N_v = 5
+    n_ok = INT32_MAX // 1331
+    assert lib.sq_index_capacity_bound(ct.byref(g), n_ok) <= INT32_MAX
+    assert lib.sq_index_capacity_bound(ct.byref(g), n_ok + 1) > INT32_MAX
+    b, io = _batch(), _batch_io()
+    b.scenes[1].n_prims = n_ok + 1
+    t = L.SqTuning(8, 4, 0, 0, 4)
+    calls = (lambda: lib.sq_batch_build_index(ct.byref(b), ct.byref(io), 0x100000, 1 << 40, None),
+             lambda: lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 40, None),
+             lambda: lib.sq_batch_render_bwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 40, None),
+             lambda: lib.sq_batch_step(ct.byref(b), ct.byref(io), ct.byref(t), 0x100000, 1 << 40, None))
+    for call in calls:
+        assert call() == L.SQ_ERR_UNSUPPORTED
+        assert "int32" in lib.sq_last_error().decode()
+    b.scenes[1].n_prims = n_ok
+    b.scenes[2].index_capacity = INT32_MAX + 1
+    for call in calls:
+        assert call() == L.SQ_ERR_UNSUPPORTED
+    # single-scene index build: the capacity alone
+    ix = _index()
+    ix.capacity = INT32_MAX + 1
+    assert lib.sq_build_index(ct.byref(g), ct.byref(_prims()), ct.byref(ix), 0x100000, 1 << 40,
+                              None) == L.SQ_ERR_UNSUPPORTED
+
+
+def test_checkpoint_length_and_chunk_are_checked():
+    """ckpt_len must hold ceil(L/K) * rays floats for the call's chunk K, and a
+    batched forward writes checkpoints only with a chunk the backward takes."""
+    lib = L.load()
+    b = _batch()                                  # L = 100, 3 scenes x 2 x 9 x 13 rays
+    rays = 3 * 2 * 9 * 13
+    io = _batch_io()
+    w = L.SqLossWeights(2.0, 0.05)
+    for K, chunk in ((4, 0), (8, 8), (16, 16)):
+        t = L.SqTuning(8, 4, 0, 0, chunk)
+        need = -(-100 // K) * rays
+        io.ckpt_len = need - 1
+        for rc in (lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 40, None),
+                   lib.sq_batch_render_bwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 40, None),
+                   lib.sq_batch_render_fwd_loss(ct.byref(b), ct.byref(io), ct.byref(w), ct.byref(t), 0x100000,
+                                                1 << 40, None),
+                   lib.sq_batch_step(ct.byref(b), ct.byref(io), ct.byref(t), 0x100000, 1 << 40, None)):
+            assert rc == L.SQ_ERR_CAPACITY
+            assert "ckpt_len" in lib.sq_last_error().decode()
+    # the autotuner checks every candidate before timing any
+    io.ckpt_len = -(-100 // 8) * rays
+    cands = (L.SqTuning * 2)(L.SqTuning(8, 4, 0, 0, 8), L.SqTuning(8, 4, 0, 0, 4))
+    best = ct.c_int32(-1)
+    assert lib.sq_batch_autotune(ct.byref(b), ct.byref(io), cands, 2, 1, ct.byref(best), None, 0x100000, 1 << 40,
+                                 None) == L.SQ_ERR_CAPACITY
+    # a chunk the backward cannot take is refused for checkpoints
+    io.ckpt_len = 1 << 40
+    for chunk in (1, 2, 3, 5, 32):
+        t = L.SqTuning(8, 4, 0, 0, chunk)
+        assert lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 40,
+                                       None) == L.SQ_ERR_INVALID
+        assert lib.sq_batch_render_fwd_loss(ct.byref(b), ct.byref(io), ct.byref(w), ct.byref(t), 0x100000, 1 << 40,
+                                            None) == L.SQ_ERR_INVALID
