@@ -117,14 +117,14 @@ __global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const 
     r[15] = opacity[k];
     // f >= max(|u|,|v|,|w|)^(2/eps1): culled where that bound reaches F_CULL
     r[16] = exp2f(0.5f * e1 * log2f(F_CULL));
-    r[17] = is[0]; r[18] = is[1]; r[19] = is[2];
     int box[3];
     prim_box(g, means + 3 * k, quats + 4 * k, scales + 3 * k, eps + 2 * k, opacity + k, box);
     uint32_t glo, hig;
     box_words(box, glo, hig);
-    r[20] = __uint_as_float(glo); r[21] = __uint_as_float(hig);
+    r[R_GLO] = __uint_as_float(glo); r[R_HIG] = __uint_as_float(hig);
+    r[R_AM1] = r[12] - 1.0f; r[R_BM1] = r[13] - 1.0f; r[R_EM1] = r[14] - 1.0f;
     r[22] = __int_as_float(box[0]); r[23] = __int_as_float(box[1]); r[24] = __int_as_float(box[2]);
-    r[25] = r[26] = r[27] = 0.0f;
+    r[R_INVS] = is[0]; r[R_INVS + 1] = is[1]; r[R_INVS + 2] = is[2];
     for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < C ? logits[(size_t)k * C + c] : 0.0f;
 }
 
@@ -463,10 +463,10 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 // the union walk runs only on grids whose cells fit the packed form
                 const uint32_t cell = act ? pack_cell(cur.ix, cur.iy, cur.iz) : PV_DEAD;
                 for_each_marked<true>(bm, nw, lane, [&](int k) {
-                    Pinned<22> rr;
+                    Pinned<19> rr;
                     Pinned<CP> lg;
                     pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
-                    if (in_box(cell, __float_as_uint(rr[20]), __float_as_uint(rr[21]))) add_pair(k, rr, lg);
+                    if (in_box(cell, __float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_HIG]))) add_pair(k, rr, lg);
                 });
                 wave_lds_sync();
             } else {
@@ -714,36 +714,33 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
 // eq:sq_occupancy_prob with f of Sec. "SuperQuadrics"), added to an
 // accumulator row WITHOUT the primitive's constant factors; k_finalize
 // multiplies each row entry by its factor once per primitive (acc_factor).
-// With dfn = p dL/dp = -dL/df, Bs = B / ln 2, Zs = Z / ln 2 and base-2 logs:
+// With dfn = p dL/dp = -dL/df, Bs = B / ln 2, Zs = Z / ln 2, base-2 logs and
+// the split powers of eval_pair (B/A = q_A, X/u = sign(u) q_u, ...):
 //   x[A_SIG]      += dL/da_j p                         (factor 1)
 //   x[A_E1]       += dfn (e Bs log2 A + b Zs log2|w|)  (factor  ln2^2 b / 2)
 //   x[A_E2]       += dfn (Bs log2 A - a Bs/A S)        (factor -ln2^2 e a / 2)
 //                    S = X log2|u| + Y log2|v|
 //   g = dfn (Bs/A X/u, Bs/A Y/v, Zs/w)                 (factors -ln2 e a/s_x,
 //   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c         -ln2 e a/s_y, -ln2 b/s_z)
-// Where |u|, |v|, |w| or A is 0 its log2 and reciprocal are infinite, but the
-// power they multiply (X, Y, Zs, Bs) is then exactly 0, and so is the limit of
-// the product; those products use the legacy multiply (0 x anything = 0), so
-// no compare or select is needed.  In particular the derivative along an axis
-// where the coordinate is exactly 0 comes out as 0.
+// Where |u|, |v|, |w| or A is 0 its log2 is -inf, but the power it multiplies
+// (X, Y, Zs, Bs) is then exactly 0, and so is the limit of the product; those
+// products use the legacy multiply (0 x anything = 0), so no compare or select
+// is needed.  The same multiply keeps an infinite q_A (A = 0 with e < 1) out of
+// the sums: every factor it meets (X/u, Y/v, S) is 0 there.
 // ---------------------------------------------------------------------------
-extern "C" __device__ float sqr_fmul_legacy(float, float) __asm("llvm.amdgcn.fmul.legacy");
-__device__ __forceinline__ float mul0(float zero_wins, float x) { return sqr_fmul_legacy(zero_wins, x); }
-
 template <int VP, typename RecT>
 __device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, const float dd[3], float dfn,
                                              float da, float x[VP]) {
     const float a_ = r[12], b_ = r[13], e_ = r[14];
-    const float bia = mul0(ev.Bs, hw_rcp(ev.A));
-    const float db = dfn * bia;
-    const float g0 = db * mul0(ev.X, hw_rcp(ev.u));
-    const float g1 = db * mul0(ev.Y, hw_rcp(ev.v));
-    const float g2 = dfn * mul0(ev.Zs, hw_rcp(ev.w));
+    const float db = mul0(dfn, ev.qA);
+    const float g0 = mul0(with_sign_of(ev.qu, ev.u), db);
+    const float g1 = mul0(with_sign_of(ev.qv, ev.v), db);
+    const float g2 = dfn * with_sign_of(ev.qw, ev.w);
     const float bla = mul0(ev.Bs, ev.lA);
     const float S = mul0(ev.X, ev.lu) + mul0(ev.Y, ev.lv);
     x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
     x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * mul0(ev.Zs, ev.lw)), x[A_E1]);
-    x[A_E2] = fmaf(dfn, fmaf(-a_, bia * S, bla), x[A_E2]);
+    x[A_E2] = fmaf(dfn, fmaf(-a_, mul0(S, ev.qA), bla), x[A_E2]);
     x[A_XS + 0] += g0; x[A_XS + 1] += g1; x[A_XS + 2] += g2;
     x[A_R + 0] = fmaf(g0, dd[0], x[A_R + 0]);
     x[A_R + 1] = fmaf(g0, dd[1], x[A_R + 1]);
@@ -763,10 +760,11 @@ __device__ __forceinline__ float acc_factor(cf_ptr r, int vi) {
     const float fu = -LN2 * e_ * a_;
     if (vi == A_E1) return 0.5f * LN2 * LN2 * b_;
     if (vi == A_E2) return -0.5f * LN2 * LN2 * e_ * a_;
-    if (vi >= A_XS && vi < A_XS + 3) return vi == A_XS + 2 ? -LN2 * b_ * r[19] : fu * r[17 + vi - A_XS];
+    if (vi >= A_XS && vi < A_XS + 3)
+        return vi == A_XS + 2 ? -LN2 * b_ * r[R_INVS + 2] : fu * r[R_INVS + vi - A_XS];
     if (vi >= A_R && vi < A_R + 9) {
         const int i = (vi - A_R) / 3;
-        return i == 2 ? -LN2 * b_ * r[19] : fu * r[17 + i];
+        return i == 2 ? -LN2 * b_ * r[R_INVS + 2] : fu * r[R_INVS + i];
     }
     return 1.0f;
 }
@@ -1060,35 +1058,42 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
         for_each_marked(bm, nw, lane, [&](int k) {
             const cf_ptr r = X.rec + (size_t)k * REC;
-            Pinned<22> rr;
+            Pinned<19> rr;
             Pinned<CP> lg;
             pin2(r, rr, X.lgp + (size_t)k * CP, lg);
-            const uint32_t glo = __float_as_uint(rr[20]), hig = __float_as_uint(rr[21]);
+            const uint32_t glo = __float_as_uint(rr[R_GLO]), hig = __float_as_uint(rr[R_HIG]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = in_box(pv[jj], glo, hig); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            float gam = 0.0f;
-#pragma unroll
-            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
             const float sig = rr[15];
+            float pj[KC];     // p of this lane's samples (0: not listed or culled)
             bool hit = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
+                pj[jj] = 0.0f;
                 if (mem[jj]) {
                     if (STATS) { st[1] += 1; if (pair_kept(r, sx[jj], sy[jj], sz[jj])) st[2] += 1; }
                     const float p = eval_p(rr, sx[jj], sy[jj], sz[jj]);
-                    if (p != 0.0f) {
-                        a[jj] = fmaf(p, sig, a[jj]);
-                        G[jj] = fmaf(p, gam, G[jj]);
-                        hit = true;
-                    }
+                    // (with p = 0 the sum keeps its bits, as in the forward, which skips)
+                    a[jj] = fmaf(p, sig, a[jj]);
+                    pj[jj] = p;
+                    hit |= p != 0.0f;
                 }
             }
-            // p = 0 for every lane and sample: the adjoint of k is 0 in this
-            // chunk, so pass 2 need not visit it
-            if (wave_ballot(hit) == 0 && lane == 0) bm[k >> 5] &= ~(1u << (k & 31));
+            if (wave_ballot(hit) == 0) {
+                // p = 0 for every lane and sample: the adjoint of k is 0 in this
+                // chunk, so pass 2 need not visit it
+                if (lane == 0) bm[k >> 5] &= ~(1u << (k & 31));
+                return;
+            }
+            // G_j += p gamma_k with gamma_k = <g_S, c_k>, only for primitives that count
+            float gam = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+#pragma unroll
+            for (int jj = 0; jj < KC; ++jj) G[jj] = fmaf(pj[jj], gam, G[jj]);
         });
 
         // ---- compositing and its adjoint (per lane) -------------------------
@@ -1130,7 +1135,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             Pinned<22> rr;
             Pinned<CP> lg;
             pin2(r, rr, X.lgp + (size_t)k * CP, lg);
-            const uint32_t glo = __float_as_uint(rr[20]), hig = __float_as_uint(rr[21]);
+            const uint32_t glo = __float_as_uint(rr[R_GLO]), hig = __float_as_uint(rr[R_HIG]);
             bool mem[KC];
             bool anym = false;
 #pragma unroll

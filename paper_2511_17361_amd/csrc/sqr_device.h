@@ -19,13 +19,16 @@ namespace sqr {
 //   [12]     a = 2/eps2   [13] b = 2/eps1   [14] e = eps2/eps1
 //   [15]     sigma
 //   [16]     r_cull: max(|u|,|v|,|w|) >= r_cull  =>  f >= F_CULL
-//   [17..19] 1/s
-//   [20..21] the same box as [22..24] in the packed-cell form of box_words
+//   [17..18] the clipped box of [22..24] in the packed-cell form of box_words
 //            (int bits; meaningful on grids within PV_MAX_XY x PV_MAX_XY x PV_MAX_Z)
+//   [19..21] a - 1, b - 1, e - 1 (the exponents of the split powers the
+//            adjoint evaluates, eval_pair)
 //   [22..24] clipped neighbourhood box per axis, int bits lo | hi << 16
 //            (the primitive is listed in voxel v iff v lies in this box)
-//   [25..27] unused
+//   [25..27] 1/s
+// The forward walks read [0..18], the adjoint [0..21].
 // ---------------------------------------------------------------------------
+constexpr int R_GLO = 17, R_HIG = 18, R_AM1 = 19, R_BM1 = 20, R_EM1 = 21, R_INVS = 25;
 constexpr int REC = 28;
 constexpr int EMPTY_BOX = 0x7fff7fff;
 constexpr float F_CULL = 110.0f;          // exp(-110) = 1.7e-48: 0 in float32
@@ -123,8 +126,8 @@ __device__ __forceinline__ int pinned_centre_axis(float m, float lo, float inv, 
 // as long as a walk uses them.  The empty asm makes each value opaque, so the
 // compiler keeps it in its register instead of re-issuing the scalar load
 // (and waiting for it) at every use, and the loads of one group are issued
-// together behind a single wait.  A record needs its first 17 entries for the
-// pair evaluation, 22 with the packed-cell box words.
+// together behind a single wait.  The forward's pair evaluation needs the
+// record's first 17 entries, 19 with the packed-cell box words; the adjoint 22.
 template <int N>
 struct Pinned {
     float v[N];
@@ -155,22 +158,41 @@ __device__ __forceinline__ void pin2(cf_ptr r, Pinned<N>& a, cf_ptr q, Pinned<M>
 // ---------------------------------------------------------------------------
 // Pair evaluation p_o(x, S_k) = exp(-f(R(x - m)/s)) (Eq. eq:sq_occupancy_prob).
 // ---------------------------------------------------------------------------
-struct PairEval {
-    float u, v, w;         // canonical coordinates x_S / s
-    float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
-    float X, Y, A, lA;     // |u|^a, |v|^a, A = X + Y, log2 A
-    float Bs, Zs;          // A^e / ln 2, |w|^b / ln 2
-    float p;
-};
-
 // log2(1 / ln 2): 2^(x + L2_LOG2E) = 2^x / ln 2
 constexpr float L2_LOG2E = 0.5287663729448977f;
 
-// Evaluation for the adjoint.  B and Z are carried divided by ln 2 (one FMA
-// each instead of a multiply), so p = 2^-(Bs + Zs) needs no extra scaling;
-// the adjoint's per-primitive factors absorb the ln 2.  p is computed by the
-// same operations as in eval_p, so both give the same bits.  Returns false
-// when the pair is culled (float32 exp(-f) would be exactly 0).
+// 0 * anything = 0 (v_mul_legacy_f32): the products below whose first factor
+// vanishes exactly where the second is infinite (a power times the log or the
+// reciprocal of its base) take their limit, 0, with no compare or select.
+extern "C" __device__ float sqr_fmul_legacy(float, float) __asm("llvm.amdgcn.fmul.legacy");
+__device__ __forceinline__ float mul0(float zero_wins, float x) { return sqr_fmul_legacy(zero_wins, x); }
+// |q| with the sign of x (q >= 0)
+__device__ __forceinline__ float with_sign_of(float q, float x) {
+    return __uint_as_float(__float_as_uint(q) | (__float_as_uint(x) & 0x80000000u));
+}
+
+// Evaluation for the adjoint.  Each power is split off its base, X = q_u |u|
+// with q_u = |u|^(a-1) = 2^((a-1) log2|u|), and likewise Y, Z and B = A^e =
+// q_A A, so the ratios the derivative chain needs come without reciprocals:
+// X/u = sign(u) q_u, Y/v = sign(v) q_v, Z/w = sign(w) q_w, B/A = q_A.  Z and
+// B are carried divided by ln 2 (through the exponent of q_w and q_A), so
+// p = 2^-(Bs + Zs) needs no multiply; the adjoint's per-primitive factors
+// absorb the ln 2.  p agrees with eval_p's to rounding (not bit for bit).
+// At a base that is exactly 0 (a sample on a principal plane of the
+// primitive) the power's log is -inf: (k-1) log2 0 is 0 for k = 1 (legacy
+// multiply) and -inf for k > 1, so q_u, q_v and q_w stay finite for a, b >= 1
+// (eps1, eps2 <= 2, the paper's parameter range).  q_A is infinite at A = 0
+// when e < 1; pair_adjoint multiplies it only by factors that vanish there.
+// Returns false when the pair is culled (float32 exp(-f) would be exactly 0).
+struct PairEval {
+    float u, v, w;         // canonical coordinates x_S / s
+    float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
+    float qu, qv, qw;      // |u|^(a-1), |v|^(a-1), |w|^(b-1) / ln 2
+    float X, Y, A, lA;     // |u|^a, |v|^a, A = X + Y, log2 A
+    float qA, Bs, Zs;      // A^(e-1) / ln 2, A^e / ln 2, |w|^b / ln 2
+    float p;
+};
+
 template <typename RecT>
 __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, float z,
                                           float dxyz[3], PairEval& e) {
@@ -185,13 +207,16 @@ __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, flo
     e.lu = hw_log2(au);
     e.lv = hw_log2(av);
     e.lw = hw_log2(aw);
-    const float a = rec[12], b = rec[13], ee = rec[14];
-    e.X = hw_exp2(a * e.lu);
-    e.Y = hw_exp2(a * e.lv);
-    e.Zs = hw_exp2(fmaf(b, e.lw, L2_LOG2E));
+    e.qu = hw_exp2(mul0(rec[R_AM1], e.lu));
+    e.qv = hw_exp2(mul0(rec[R_AM1], e.lv));
+    e.qw = hw_exp2(mul0(rec[R_BM1], e.lw) + L2_LOG2E);
+    e.X = mul0(e.qu, au);
+    e.Y = mul0(e.qv, av);
+    e.Zs = mul0(e.qw, aw);
     e.A = e.X + e.Y;
     e.lA = hw_log2(e.A);
-    e.Bs = hw_exp2(fmaf(ee, e.lA, L2_LOG2E));
+    e.qA = hw_exp2(mul0(rec[R_EM1], e.lA) + L2_LOG2E);
+    e.Bs = mul0(e.qA, e.A);
     e.p = hw_exp2(-(e.Bs + e.Zs));
     return true;
 }
@@ -205,8 +230,10 @@ __device__ __forceinline__ bool pair_kept(cf_ptr rec, float x, float y, float z)
     return fmaxf(fmaxf(fabsf(u), fabsf(v)), fabsf(w)) < rec[16];
 }
 
-// Evaluation of p alone (0 when culled), by eval_pair's operations: B and Z
-// divided by ln 2 through the exponent, so p = 2^-(Bs + Zs) takes no multiply.
+// Evaluation of p alone (0 when culled): B and Z divided by ln 2 through the
+// exponent, so p = 2^-(Bs + Zs) takes no multiply.  The forward, the
+// backward's recompute and the voxelisation all call this, so they agree bit
+// for bit.
 template <typename RecT>
 __device__ __forceinline__ float eval_p(const RecT& rec, float x, float y, float z) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
