@@ -451,6 +451,32 @@ sq_status sq_batch_autotune(const sq_batch* batch, const sq_batch_io* io, const 
                             int32_t n_candidates, int32_t reps, int32_t* best_index, float* ms_per_candidate,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free forward, for callers that cannot allocate device memory:
+ * code under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.
+ * ------------------------------------------------------------------------ */
+/* Bytes of the library's fixed per-GPU scratch array (16 MiB).  Every GPU the
+ * library runs on holds one such array until the process ends. */
+#define SQ_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* sq_render_fwd with no workspace argument: its scratch space (the prepared
+ * primitive records, the scene table, the work counters) is the library's
+ * fixed device array of SQ_NOALLOC_SCRATCH_BYTES on the current device, and
+ * the call allocates nothing (no hipMalloc, no allocating library routine).
+ * The caller still owns every input and output, as for sq_render_fwd, and the
+ * results are those of sq_render_fwd bit for bit.  A call whose scratch need
+ * (sq_render_workspace) exceeds the array returns SQ_ERR_CAPACITY before
+ * touching the device.  All calls on one GPU share its array, which keeps the
+ * last call's contents (each call rewrites what it reads); calls that overlap
+ * on one GPU (concurrent streams or threads) race and must be serialised by
+ * the caller.  The first call on a device looks the array's address up once
+ * (hipGetSymbolAddress) with that device current. */
+sq_status sq_render_fwd_noalloc(const sq_grid* grid, const sq_index* idx, const sq_prims* prims,
+                                const sq_rays* rays, const sq_march* march,
+                                float* depth, float* sem, float* probs, float* t_final, float* ckpt,
+                                int64_t* stats, const sq_tuning* tuning, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

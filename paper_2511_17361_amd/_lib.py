@@ -26,8 +26,9 @@ EXPORTED = [
     "sq_batch_step_graph_create", "sq_graph_launch", "sq_graph_destroy", "sq_batch_autotune",
     "sq_voxelise_workspace", "sq_voxelise", "sq_batch_voxelise",
     "sq_render_fwd_loss", "sq_batch_render_fwd_loss", "sq_batch_train_step", "sq_batch_train_graph_create",
-    "sq_sq_major_workspace", "sq_render_bwd_sq_major", "sq_batch_tile_stop_len",
+    "sq_sq_major_workspace", "sq_render_bwd_sq_major", "sq_batch_tile_stop_len", "sq_render_fwd_noalloc",
 ]
+SQ_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class SqGrid(ct.Structure):
@@ -124,6 +125,10 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.sq_render_fwd.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch),
                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                   P(SqTuning), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_render_fwd_noalloc.restype = ct.c_int32
+    lib.sq_render_fwd_noalloc.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch),
+                                          ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                          ct.c_void_p, P(SqTuning), ct.c_void_p]
     lib.sq_render_bwd.restype = ct.c_int32
     lib.sq_render_bwd.argtypes = [P(SqGrid), P(SqIndex), P(SqPrims), P(SqRays), P(SqMarch),
                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, P(SqGrads), ct.c_void_p, P(SqTuning),

@@ -258,6 +258,36 @@ def render_fwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt_every: 
     return out
 
 
+def render_fwd_noalloc(grid, index: Index, prims: Prims, rays: Rays, march, ckpt_every: int = 0,
+                       probs: bool = True, tuning: Optional[Tuning] = None, stream=None,
+                       out: Optional[dict] = None) -> dict:
+    """sq_render_fwd_noalloc: sq_render_fwd with its scratch in the library's
+    fixed per-GPU array (no workspace).  The library allocates nothing; this
+    binding allocates the outputs unless `out` (same keys as render_fwd's)
+    is given."""
+    lib = L.load()
+    grid, march = Grid.of(grid), March.of(march)
+    dev = prims.means.device
+    cams, H, W = rays.shape
+    C = prims.n_classes
+    R = cams * H * W
+    if out is None:
+        out = dict(depth=torch.empty((cams, H, W), device=dev), sem=torch.empty((cams, C, H, W), device=dev),
+                   t_final=torch.empty((cams, H, W), device=dev))
+        if probs:
+            out["probs"] = torch.empty((cams, C, H, W), device=dev)
+        if ckpt_every > 0:
+            out["ckpt"] = torch.empty((-(-march.n_samples // ckpt_every), R), device=dev)
+    g, p, r, m = grid.c(), prims.c(), rays.c(), march.c(ckpt_every)
+    ix = index.c()
+    t = (tuning or Tuning()).c()
+    L.check(lib.sq_render_fwd_noalloc(ct.byref(g), ct.byref(ix), ct.byref(p), ct.byref(r), ct.byref(m),
+                                      _ptr(out["depth"]), _ptr(out["sem"]), _ptr(out.get("probs")),
+                                      _ptr(out["t_final"]), _ptr(out.get("ckpt")), None, ct.byref(t),
+                                      _stream_handle(stream)))
+    return out
+
+
 def render_bwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt: torch.Tensor, ckpt_every: int,
                g_depth: Optional[torch.Tensor], g_sem: Optional[torch.Tensor], tuning: Optional[Tuning] = None,
                stream=None, ws: Optional[Workspace] = None, out: Optional[dict] = None,

@@ -26,6 +26,18 @@ sq_status fail(sq_status code, const char* fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+int32_t sqr::set_error(int32_t code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+namespace {
+
 sq_status ok() {
     g_err[0] = '\0';
     return SQ_OK;

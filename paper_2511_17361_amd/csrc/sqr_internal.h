@@ -110,4 +110,7 @@ hipError_t launch_batch_bwd_sq_major(const GridDev& g, const BatchDesc& d, const
 // whether the primitive-major backward applies to these arguments
 bool bwd_primitive_major_ok(const GridDev& g, int max_n, int K, int wpb);
 
+// Records the thread's sq_last_error() message and returns `code`.
+int32_t set_error(int32_t code, const char* fmt, ...);
+
 }  // namespace sqr

@@ -368,3 +368,22 @@ def test_checkpoint_length_and_chunk_are_checked():
                                        None) == L.SQ_ERR_INVALID
         assert lib.sq_batch_render_fwd_loss(ct.byref(b), ct.byref(io), ct.byref(w), ct.byref(t), 0x100000, 1 << 40,
                                             None) == L.SQ_ERR_INVALID
+
+
+def test_noalloc_forward_refuses_scenes_beyond_its_array_without_touching_the_device():
+    """The allocation-free forward checks its scratch need on the host: a scene
+    whose workspace exceeds the fixed array, or invalid arguments, are refused
+    before any device call (the pointers here are never dereferenced)."""
+    lib = L.load()
+    big = _prims(n=200000, C=32)
+    assert lib.sq_render_workspace(ct.byref(_grid()), ct.byref(big), ct.byref(_rays()),
+                                   ct.byref(_march())) > L.SQ_NOALLOC_SCRATCH_BYTES
+    t = L.SqTuning(8, 4, 0, 0, 0)
+    rc = lib.sq_render_fwd_noalloc(ct.byref(_grid()), ct.byref(_index()), ct.byref(big), ct.byref(_rays()),
+                                   ct.byref(_march()), FAKE, FAKE, None, FAKE, None, None, ct.byref(t), None)
+    assert rc == L.SQ_ERR_CAPACITY
+    assert "fixed" in lib.sq_last_error().decode()
+    bad = _grid(nv=-1)
+    rc = lib.sq_render_fwd_noalloc(ct.byref(bad), ct.byref(_index()), ct.byref(_prims()), ct.byref(_rays()),
+                                   ct.byref(_march()), FAKE, FAKE, None, FAKE, None, None, ct.byref(t), None)
+    assert rc == L.SQ_ERR_INVALID
