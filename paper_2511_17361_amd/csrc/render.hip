@@ -714,19 +714,20 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
 // eq:sq_occupancy_prob with f of Sec. "SuperQuadrics"), added to an
 // accumulator row WITHOUT the primitive's constant factors; k_finalize
 // multiplies each row entry by its factor once per primitive (acc_factor).
-// With dfn = p dL/dp = -dL/df, Bs = B / ln 2, Zs = Z / ln 2, base-2 logs and
-// the split powers of eval_pair (B/A = q_A, X/u = sign(u) q_u, ...):
-//   x[A_SIG]      += dL/da_j p                         (factor 1)
-//   x[A_E1]       += dfn (e Bs log2 A + b Zs log2|w|)  (factor  ln2^2 b / 2)
-//   x[A_E2]       += dfn (Bs log2 A - a Bs/A S)        (factor -ln2^2 e a / 2)
+// With dfn = p dL/dp = -dL/df, base-2 logs and the split powers of eval_pair
+// (B/A = q_A, X/u = sign(u) q_u, ...):
+//   x[A_SIG]      += dL/da_j p                       (factor 1)
+//   x[A_E1]       += dfn (e B log2 A + b Z log2|w|)  (factor  ln2 b / 2)
+//   x[A_E2]       += dfn (B log2 A - a B/A S)        (factor -ln2 e a / 2)
 //                    S = X log2|u| + Y log2|v|
-//   g = dfn (Bs/A X/u, Bs/A Y/v, Zs/w)                 (factors -ln2 e a/s_x,
-//   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c         -ln2 e a/s_y, -ln2 b/s_z)
+//   g = dfn (B/A X/u, B/A Y/v, Z/w)                  (factors -e a/s_x,
+//   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c       -e a/s_y, -b/s_z)
 // Where |u|, |v|, |w| or A is 0 its log2 is -inf, but the power it multiplies
-// (X, Y, Zs, Bs) is then exactly 0, and so is the limit of the product; those
+// (X, Y, Z, B) is then exactly 0, and so is the limit of the product; those
 // products use the legacy multiply (0 x anything = 0), so no compare or select
 // is needed.  The same multiply keeps an infinite q_A (A = 0 with e < 1) out of
-// the sums: every factor it meets (X/u, Y/v, S) is 0 there.
+// the sums: every factor it meets (X/u, Y/v, S) is 0 there.  With p = 0 every
+// term is exactly 0, so callers need not test p.
 // ---------------------------------------------------------------------------
 template <int VP, typename RecT>
 __device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, const float dd[3], float dfn,
@@ -735,11 +736,11 @@ __device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, 
     const float db = mul0(dfn, ev.qA);
     const float g0 = mul0(with_sign_of(ev.qu, ev.u), db);
     const float g1 = mul0(with_sign_of(ev.qv, ev.v), db);
-    const float g2 = dfn * with_sign_of(ev.qw, ev.w);
-    const float bla = mul0(ev.Bs, ev.lA);
+    const float g2 = mul0(dfn, with_sign_of(ev.qw, ev.w));
+    const float bla = mul0(ev.B, ev.lA);
     const float S = mul0(ev.X, ev.lu) + mul0(ev.Y, ev.lv);
     x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
-    x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * mul0(ev.Zs, ev.lw)), x[A_E1]);
+    x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * mul0(ev.Z, ev.lw)), x[A_E1]);
     x[A_E2] = fmaf(dfn, fmaf(-a_, mul0(S, ev.qA), bla), x[A_E2]);
     x[A_XS + 0] += g0; x[A_XS + 1] += g1; x[A_XS + 2] += g2;
     x[A_R + 0] = fmaf(g0, dd[0], x[A_R + 0]);
@@ -757,14 +758,14 @@ __device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, 
 // pair_adjoint); 1 for the opacity and the logits.
 __device__ __forceinline__ float acc_factor(cf_ptr r, int vi) {
     const float a_ = r[12], b_ = r[13], e_ = r[14];
-    const float fu = -LN2 * e_ * a_;
-    if (vi == A_E1) return 0.5f * LN2 * LN2 * b_;
-    if (vi == A_E2) return -0.5f * LN2 * LN2 * e_ * a_;
+    const float fu = -e_ * a_;
+    if (vi == A_E1) return 0.5f * LN2 * b_;
+    if (vi == A_E2) return -0.5f * LN2 * e_ * a_;
     if (vi >= A_XS && vi < A_XS + 3)
-        return vi == A_XS + 2 ? -LN2 * b_ * r[R_INVS + 2] : fu * r[R_INVS + vi - A_XS];
+        return vi == A_XS + 2 ? -b_ * r[R_INVS + 2] : fu * r[R_INVS + vi - A_XS];
     if (vi >= A_R && vi < A_R + 9) {
         const int i = (vi - A_R) / 3;
-        return i == 2 ? -LN2 * b_ * r[R_INVS + 2] : fu * r[R_INVS + i];
+        return i == 2 ? -b_ * r[R_INVS + 2] : fu * r[R_INVS + i];
     }
     return 1.0f;
 }
@@ -1173,7 +1174,8 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                     float dd[3];
                     const bool kept = eval_pair(rr, sx[jj], sy[jj], sz[jj], dd, ev);
                     if (STATS) { st[4] += 1; if (kept) st[5] += 1; }
-                    if (kept && ev.p > 0.0f) {
+                    // (a kept pair whose p underflows to 0 adds exactly 0)
+                    if (kept) {
                         contrib = true;
                         const float da = a[jj], w = G[jj];
                         const float dfn = ev.p * fmaf(da, sig, w * gam);

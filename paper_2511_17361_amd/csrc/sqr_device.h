@@ -174,11 +174,9 @@ __device__ __forceinline__ float with_sign_of(float q, float x) {
 // Evaluation for the adjoint.  Each power is split off its base, X = q_u |u|
 // with q_u = |u|^(a-1) = 2^((a-1) log2|u|), and likewise Y, Z and B = A^e =
 // q_A A, so the ratios the derivative chain needs come without reciprocals:
-// X/u = sign(u) q_u, Y/v = sign(v) q_v, Z/w = sign(w) q_w, B/A = q_A.  Z and
-// B are carried divided by ln 2 (through the exponent of q_w and q_A), so
-// p = 2^-(Bs + Zs) needs no multiply; the adjoint's per-primitive factors
-// absorb the ln 2.  p agrees with eval_p's to rounding (not bit for bit).
-// At a base that is exactly 0 (a sample on a principal plane of the
+// X/u = sign(u) q_u, Y/v = sign(v) q_v, Z/w = sign(w) q_w, B/A = q_A, and
+// p = 2^-((B + Z) log2 e).  p agrees with eval_p's to rounding (not bit for
+// bit).  At a base that is exactly 0 (a sample on a principal plane of the
 // primitive) the power's log is -inf: (k-1) log2 0 is 0 for k = 1 (legacy
 // multiply) and -inf for k > 1, so q_u, q_v and q_w stay finite for a, b >= 1
 // (eps1, eps2 <= 2, the paper's parameter range).  q_A is infinite at A = 0
@@ -187,11 +185,13 @@ __device__ __forceinline__ float with_sign_of(float q, float x) {
 struct PairEval {
     float u, v, w;         // canonical coordinates x_S / s
     float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
-    float qu, qv, qw;      // |u|^(a-1), |v|^(a-1), |w|^(b-1) / ln 2
+    float qu, qv, qw;      // |u|^(a-1), |v|^(a-1), |w|^(b-1)
     float X, Y, A, lA;     // |u|^a, |v|^a, A = X + Y, log2 A
-    float qA, Bs, Zs;      // A^(e-1) / ln 2, A^e / ln 2, |w|^b / ln 2
+    float qA, B, Z;        // A^(e-1), A^e, |w|^b
     float p;
 };
+
+constexpr float LOG2E = 1.4426950408889634f;
 
 template <typename RecT>
 __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, float z,
@@ -209,15 +209,15 @@ __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, flo
     e.lw = hw_log2(aw);
     e.qu = hw_exp2(mul0(rec[R_AM1], e.lu));
     e.qv = hw_exp2(mul0(rec[R_AM1], e.lv));
-    e.qw = hw_exp2(mul0(rec[R_BM1], e.lw) + L2_LOG2E);
+    e.qw = hw_exp2(mul0(rec[R_BM1], e.lw));
     e.X = mul0(e.qu, au);
     e.Y = mul0(e.qv, av);
-    e.Zs = mul0(e.qw, aw);
+    e.Z = mul0(e.qw, aw);
     e.A = e.X + e.Y;
     e.lA = hw_log2(e.A);
-    e.qA = hw_exp2(mul0(rec[R_EM1], e.lA) + L2_LOG2E);
-    e.Bs = mul0(e.qA, e.A);
-    e.p = hw_exp2(-(e.Bs + e.Zs));
+    e.qA = hw_exp2(mul0(rec[R_EM1], e.lA));
+    e.B = mul0(e.qA, e.A);
+    e.p = hw_exp2((e.B + e.Z) * -LOG2E);
     return true;
 }
 
