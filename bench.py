@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=4, help="workload config (4 = 6x900x1600, 25.6k SQs)")
-    ap.add_argument("--ckpt-every", type=int, default=4)
+    ap.add_argument("--ckpt-every", type=int, default=8)
     ap.add_argument("--tile-w", type=int, default=8)
     ap.add_argument("--wpb", type=int, default=2)
     ap.add_argument("--bwd-mode", type=int, default=0, help="0 auto, 1 sample-major, 2 primitive-major")
@@ -99,8 +99,9 @@ def parse():
     ap.add_argument("--cpu-procs", type=int, default=0, help="CPU-baseline worker processes (0: every core, <= 16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the default candidate tunings first and run the fastest")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the tuning given by --tile-w/--wpb/--ckpt-every instead of timing the default "
+                         "candidates first and running the fastest")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after timing, copy a buffer of this many MiB once (HBM counter calibration)")
     return ap.parse_args()
@@ -335,9 +336,10 @@ def main():
 
     tune = api.Tuning(args.tile_w, args.wpb, args.bwd_mode, 1, args.ckpt_every)
     tuned_ms = None
-    if args.autotune:
+    cands = api.default_candidates()
+    if not args.no_autotune:
         with torch.cuda.stream(stream):
-            tune, tuned_ms = batch.autotune(api.default_candidates(), reps=2, stream=stream)
+            tune, tuned_ms = batch.autotune(cands, reps=2, stream=stream)
     torch.cuda.synchronize()
 
     # the step: index + forward with checkpoints + backward, captured once and replayed
@@ -501,7 +503,7 @@ def main():
                    "tuning": dict(tile_w=tune.tile_w, waves_per_block=tune.waves_per_block,
                                   bwd_mode=tune.bwd_mode, persistent=tune.persistent,
                                   chunk=tune.chunk or args.ckpt_every),
-                   "autotuned": bool(args.autotune)},
+                   "autotuned": not args.no_autotune},
         "fwd_ray_samples_per_s": R * Ls / (t_fwd / 1e3),
         "plain_fwd_ray_samples_per_s": R * Ls / (t_plain / 1e3),
         "rays_per_s_fwd_bwd": R / (ms_step / 1e3),
@@ -517,7 +519,8 @@ def main():
         "voxelise_pairs_per_s": sum(E) / (t_vox / 1e3),
     }
     if tuned_ms is not None:
-        result["autotune_ms"] = [round(m, 3) for m in tuned_ms]
+        result["autotune"] = [dict(tile_w=c.tile_w, waves_per_block=c.waves_per_block, chunk=c.chunk,
+                                   persistent=c.persistent, step_ms=round(m, 3)) for c, m in zip(cands, tuned_ms)]
 
     K = tune.chunk or args.ckpt_every
     if not args.no_stats:

@@ -51,7 +51,7 @@ int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
 // than the wave it buys.
 #define FWD_WPE(CP, CKPT, STATS, PERSIST) \
     ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : (!(CKPT) || (PERSIST)) ? 6 : 4)
-#define BWD_WPE(CP, KC) ((KC) == 4 && (CP) <= 17 ? 4 : 3)
+#define BWD_WPE(CP, KC) ((CP) <= 17 ? 4 : 3)
 
 // Kernel parameters shared by every render kernel.
 struct Ctx {
@@ -990,6 +990,23 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
         for (int c = 0; c < 16; ++c) lgs[c * LGS_STRIDE + lane] = gS[c];
     }
+    // gamma_k = <g_S, c_k> for this lane's ray.  At C = 17 classes 0..15 are
+    // read back from the per-wave LDS copy (the lane's column of the g_S rows),
+    // which keeps 16 registers free across the chunk loop; the summation order
+    // is the same either way.
+    const float gS16 = gS[CP - 1];
+    auto gamma_of = [&](const Pinned<CP>& lg) {
+        float gam = 0.0f;
+        if constexpr (SPLIT) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) gam = fmaf(lgs[c * LGS_STRIDE + lane], lg[c], gam);
+            gam = fmaf(gS16, lg[16], gam);
+        } else {
+#pragma unroll
+            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+        }
+        return gam;
+    };
 
     int64_t st[6] = {0, 0, 0, 0, 0, 0};
     // past the sample where the forward stopped this tile every ray is opaque
@@ -1089,10 +1106,8 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 if (lane == 0) bm[k >> 5] &= ~(1u << (k & 31));
                 return;
             }
-            // G_j += p gamma_k with gamma_k = <g_S, c_k>, only for primitives that count
-            float gam = 0.0f;
-#pragma unroll
-            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+            // G_j += p gamma_k, only for primitives that count
+            const float gam = gamma_of(lg);
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) G[jj] = fmaf(pj[jj], gam, G[jj]);
         });
@@ -1142,9 +1157,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = in_box(pv[jj], glo, hig); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
-            float gam = 0.0f;
-#pragma unroll
-            for (int c = 0; c < CP; ++c) gam = fmaf(gS[c], lg[c], gam);
+            const float gam = gamma_of(lg);
             const float sig = rr[15];
             constexpr int VR = SPLIT ? 16 : VP;     // values reduced across the wave
             float x[VR];
@@ -1207,7 +1220,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 __builtin_amdgcn_sched_barrier(0);
                 wave_lds_sync();
                 const float lgt = row_sum4(part);
-                x[15] = om * gS[16];
+                x[15] = om * gS16;
                 const float tot = transpose_reduce<16>(x, lane);
                 const int vi = lane >> 2;              // value index held by this lane
                 if ((lane & 3) == 0) atomicAdd(acc + (size_t)k * VP + (vi < 15 ? vi : A_LG + 16), tot);

@@ -17,7 +17,7 @@ def _run(*args):
 def test_help_lists_the_options():
     r = _run("--help")
     assert r.returncode == 0, r.stderr
-    for opt in ("--gpus", "--steps", "--warmup", "--cpu-rays", "--no-cpu", "--autotune", "--calib-copy-mb"):
+    for opt in ("--gpus", "--steps", "--warmup", "--cpu-rays", "--no-cpu", "--no-autotune", "--calib-copy-mb"):
         assert opt in r.stdout, opt
 
 
