@@ -210,13 +210,25 @@ def test_backward_after_a_forward_with_another_chunk_writes_nan():
         assert torch.isfinite(b.buf["g_" + k]).all(), k
 
 
-def test_bench_workload_step_gradients_on_sampled_rays():
-    """The bench's workload (6 x 1600x900 rays, 25.6k superquadrics, L = 200)
-    in the bench's launch configuration (tile 8x8, 2 waves per block,
-    primitive-major backward, persistent, K = 4) through a captured step
-    replay.  Upstream gradients are non-zero on 400 rays only, so the oracle's
-    gradients over those rays are exact; the forward is checked on them too."""
+@pytest.fixture(scope="module")
+def bench_workload():
+    """The bench's workload and the oracle's index of it (built once)."""
     sc = synth.config(4)
+    return sc, oracle.build_index(sc.prims, sc.grid)[:3]
+
+
+BENCH_TUNINGS = [(16, 2, 8), (8, 2, 8), (8, 2, 4)]
+
+
+@pytest.mark.parametrize("tw,wpb,K", BENCH_TUNINGS)
+def test_bench_workload_step_gradients_on_sampled_rays(bench_workload, tw, wpb, K):
+    """The bench's workload (6 x 1600x900 rays, 25.6k superquadrics, L = 200)
+    in the launch configurations its autotuner picks among (tile 16x4 or 8x8,
+    2 waves per block, primitive-major backward, persistent, chunk 8 or 4)
+    through a captured step replay.  Upstream gradients are non-zero on 400
+    rays only, so the oracle's gradients over those rays are exact; the
+    forward is checked on them too."""
+    sc, index = bench_workload
     C = sc.prims.n_classes
     rng = np.random.default_rng(44)
     ids = rng.choice(sc.rays.n_rays, 400, replace=False)
@@ -225,11 +237,11 @@ def test_bench_workload_step_gradients_on_sampled_rays():
     g_d[ids] = rng.standard_normal(ids.size).astype(np.float32)
     g_s[ids] = rng.standard_normal((ids.size, C)).astype(np.float32)
     cams, Hh, Ww = sc.rays.shape
-    b = _make_batch([sc], K=4)
+    b = _make_batch([sc], K=K)
     b.set_upstream(0, torch.from_numpy(g_d.reshape(cams, Hh, Ww)).cuda(),
                    torch.from_numpy(g_s.reshape(cams, Hh, Ww, C).transpose(0, 3, 1, 2).copy()).cuda())
-    tune = api.Tuning(8, 2, 0, 1, 4)
-    _say("bench workload step, sampled rays")
+    tune = api.Tuning(tw, wpb, 0, 1, K)
+    _say(f"bench workload step, sampled rays, tile {tw}, {wpb} waves per block, chunk {K}")
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         b.step(tune, stream=s)
@@ -239,7 +251,6 @@ def test_bench_workload_step_gradients_on_sampled_rays():
     torch.cuda.synchronize()
     b.release_graph()
     out = {k: v.cpu().numpy() for k, v in b.scene_outputs(0).items()}
-    index = oracle.build_index(sc.prims, sc.grid)[:3]
     ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march, index=index, ray_ids=ids)
     H.assert_depth_close(out["depth"].reshape(-1)[ids], ref["depth"], "bench workload")
     H.assert_probs_close(H.flat_sem(out["probs"])[ids], ref["probs"], "bench workload")
