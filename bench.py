@@ -68,21 +68,51 @@ def flops_bwd(fst, C):
     return recompute + adjoint
 
 
-def recorded_traffic(kernel_name):
-    """Calibrated HBM bytes per launch of `kernel_name` from the committed counter
-    runs (profiles/hbm_traffic.json), or None when the kernel sources changed
-    since those counters were taken."""
+def _source_hash():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    src = b"".join(open(os.path.join(ROOT, "paper_2511_17361_amd", "csrc", f), "rb").read()
+                   for f in ("render.hip", "sqr_device.h", "index.hip"))
+    return hashlib.sha256(src).hexdigest()[:16]
+
+
+def recorded_profile():
+    """Per-kernel counter figures of the committed profile runs
+    (profiles/render_counters.json: calibrated HBM bytes, VALU issue
+    utilisation, lane occupancy, LDS bank-conflict rate, instruction counts),
+    with `current` telling whether the kernel sources still hash to the
+    profiled version.  None when the file is absent."""
+    path = os.path.join(ROOT, "profiles", "render_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = b"".join(open(os.path.join(ROOT, "paper_2511_17361_amd", "csrc", f), "rb").read()
-                   for f in ("render.hip", "sqr_device.h"))
-    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16"):
-        return None
-    k = rec["kernels"].get(kernel_name)
-    return None if k is None else k["read_bytes"] + k["write_bytes"]
+    rec["current"] = rec.get("source_sha256_16") == _source_hash()
+    return rec
+
+
+def stage_bytes(R, C, L, K, N, V, E, probs=True, ckpt=True):
+    """Algorithmic HBM bytes of each stage (inputs read once, outputs written
+    once; lists, records and per-sample state that stay on chip are not
+    counted):
+      index:    means 12 N, counts and offsets 4 V each, ids 4 E;
+      forward:  rays 24 R, primitives 120 N, depth and t_final 4 R each, sem
+                4 C R, probs 4 C R, checkpoints 4 ceil(L/K) R;
+      backward: rays 24 R, primitives 120 N, g_D 4 R, g_S 4 C R, checkpoints
+                4 ceil(L/K) R, gradients 4 (13 + C) N."""
+    nck = -(-L // K)
+    idx = 12 * N + 8 * V + 4 * E
+    fwd = 24 * R + 120 * N + 8 * R + 4 * C * R * (2 if probs else 1) + (4 * nck * R if ckpt else 0)
+    bwd = 24 * R + 120 * N + 4 * R + 4 * C * R + 4 * nck * R + 4 * (13 + C) * N
+    return dict(index=idx, fwd=fwd, bwd=bwd)
+
+
+def form(ms, rays, L, listed, hbm_bytes=None):
+    """Rates of one form of the path over `ms` milliseconds."""
+    t = ms / 1e3
+    d = dict(ms=ms, rays_per_s=rays / t, ray_samples_per_s=rays * L / t, pairs_per_s=listed / t)
+    if hbm_bytes is not None:
+        d["hbm_gb_per_s"] = hbm_bytes / t / 1e9
+        d["hbm_frac"] = hbm_bytes / t / 1e9 / HBM_PEAK_GBS
+    return d
 
 
 def parse():
@@ -248,11 +278,17 @@ def batched_8_scenes(dev, steps, warmup):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     batch.release_graph()
+    st = torch.zeros(4, dtype=torch.int64, device=dev)
+    with torch.cuda.stream(stream):
+        batch.render_fwd(tune, stats=st, stream=stream)
+    torch.cuda.synchronize()
+    listed = int(st[1].item())
     samples = batch.n_rays * sc0.march.n_samples
     return dict(workload="8 scenes, 2k..25.6k superquadrics (94k), 6 cameras x 352x200 rays each, L=100, "
                          "step = index + forward(checkpoints) + backward, autotuned, one hipGraph replay",
                 superquadrics=sum(s.prims.n for s in scenes), rays=batch.n_rays, step_ms=ms,
-                ray_samples_per_s=samples / (ms / 1e3),
+                ray_samples_per_s=samples / (ms / 1e3), listed_pairs=listed,
+                rays_per_s=batch.n_rays / (ms / 1e3), pairs_per_s=listed / (ms / 1e3),
                 tuning=dict(tile_w=tune.tile_w, waves_per_block=tune.waves_per_block, bwd_mode=tune.bwd_mode,
                             persistent=tune.persistent, chunk=tune.chunk))
 
@@ -541,11 +577,36 @@ def main():
         f_bwd = flops_bwd(fst, C)
         ach = f_bwd / (t_bwd / 1e3) / 1e12
         kname = f"sqr::k_render_bwd_km<{api_cp(C)}, {K}, false, {'true' if tune.persistent else 'false'}>"
+        prof = recorded_profile()
+        kprof = (prof or {}).get("kernels", {}).get(kname) if prof and prof["current"] else None
+        traffic = None if kprof is None else kprof["read_bytes"] + kprof["write_bytes"]
         result["roofline"] = {"bound": "alu", "kernel": kname, "achieved": ach, "peak": VALU_PEAK_TFLOPS,
                               "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS,
-                              "traffic": recorded_traffic(kname), "flop_per_launch": f_bwd, "kernel_ms": t_bwd,
+                              "traffic": traffic, "flop_per_launch": f_bwd, "kernel_ms": t_bwd,
                               "peak_nonpacked": VALU_NONPACKED_TFLOPS,
                               "frac_nonpacked": ach / VALU_NONPACKED_TFLOPS}
+        # every form of the path at this workload: rays/s, ray-samples/s, pairs/s (the
+        # method's listed (sample, primitive) pairs), algorithmic HBM GB/s and its fraction
+        N = sum(s_.prims.n for s_ in scenes)
+        sb = stage_bytes(R, C, Ls, K, N, grid.n_voxels * len(scenes), sum(E))
+        sbp = stage_bytes(R, C, Ls, K, N, grid.n_voxels * len(scenes), sum(E), ckpt=False)
+        P = fst["listed"]
+        result["forms"] = {
+            "plain_fwd": form(t_plain, R, Ls, P, sbp["fwd"]),
+            "differentiable_fwd": form(t_fwd, R, Ls, P, sb["fwd"]),
+            "bwd": form(t_bwd, R, Ls, P, sb["bwd"]),
+            "fwd_bwd_step": form(ms_step, R, Ls, P, sb["index"] + sb["fwd"] + sb["bwd"]),
+            "index": dict(ms=t_idx, entries=sum(E), hbm_gb_per_s=sb["index"] / (t_idx / 1e3) / 1e9,
+                          hbm_frac=sb["index"] / (t_idx / 1e3) / 1e9 / HBM_PEAK_GBS),
+        }
+        if prof is not None:
+            keep = ("valu_issue_util", "valu_lane_occupancy", "lds_bank_conflict_rate", "valu_insts",
+                    "valu_trans_insts", "read_bytes", "write_bytes")
+            result["profile"] = {
+                "source": "profiles/render_counters.json (rocprofv3 counter runs of this bench, committed)",
+                "current": prof["current"], "tuning": prof.get("tuning"),
+                "kernels": {k: {f: v[f] for f in keep if f in v} for k, v in prof["kernels"].items()
+                            if k.startswith("sqr::k_render") or k.startswith("sqr::k_tile_lists")}}
 
     result["sq_major_ab"] = sq_major_ab(dev, args.steps)
     result["batched_8_scenes"] = batched_8_scenes(dev, args.steps, args.warmup)
