@@ -1640,7 +1640,7 @@ static WsSizes ws_sizes(const GridDev& g, const BatchDesc& d) {
     z.desc = align_up(sizeof(BatchDesc));
     z.queue = align_up(2 * N_XCD * QUEUE_STRIDE * sizeof(int));
     z.boxes = align_up((size_t)d.total_prims * sizeof(int4));
-    z.partials = align_up((size_t)d.n_scenes * scan_parts(g) * sizeof(int64_t));
+    z.partials = align_up(index_scratch_bytes(g, d));
     z.rec = align_up((size_t)d.total_prims * REC * sizeof(float));
     z.lgp = align_up((size_t)d.total_prims * CP * sizeof(float));
     z.acc = align_up((size_t)d.total_prims * acc_row(CP) * sizeof(float));

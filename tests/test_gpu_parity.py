@@ -67,6 +67,19 @@ def test_index_bitexact_config1_and_repeatable():
     assert torch.equal(idx.offsets, idx2.offsets)
 
 
+def test_index_bitexact_dense_tiles_beyond_the_sort():
+    """6,000 primitives crowded into a few voxel tiles: the tiles whose binned
+    candidate slice exceeds the in-LDS sort stream every primitive of the
+    scene instead, the others sort their slice; both give the oracle's lists
+    bit for bit (ascending ids)."""
+    sc = random_scene(6, n=6000, nv=5, dims=(24, 20, 18), voxel=0.5, lo=(-6.0, -5.0, -4.5))
+    rng = np.random.default_rng(6)
+    # two thirds of the centres inside a 1.2 m cube, the rest spread over the grid
+    sc.prims.means[:4000] = rng.uniform(-0.6, 0.6, (4000, 3)).astype(np.float32)
+    _say("index dense tiles")
+    _index_case(sc)
+
+
 def test_index_capacity_overflow_is_reported():
     sc = random_scene(5, n=50, nv=3, dims=(12, 12, 6))
     grid, prims, _, _ = H.gpu_scene(sc)
