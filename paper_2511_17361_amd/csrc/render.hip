@@ -1179,7 +1179,6 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 for (int i = 0; i < VR; ++i) x[i] = 0.0f;
             }
             float om = 0.0f;          // sum_j w_j p_jk
-            bool contrib = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
                 if (mem[jj]) {
@@ -1189,7 +1188,6 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                     if (STATS) { st[4] += 1; if (kept) st[5] += 1; }
                     // (a kept pair whose p underflows to 0 adds exactly 0)
                     if (kept) {
-                        contrib = true;
                         const float da = a[jj], w = G[jj];
                         const float dfn = ev.p * fmaf(da, sig, w * gam);
                         pair_adjoint<VR>(rr, ev, dd, dfn, da, x);
@@ -1197,7 +1195,10 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                     }
                 }
             }
-            if (wave_ballot(contrib) == 0) return;
+            // (no test for a visit without a kept pair: pass 1 dropped every
+            // primitive with p = 0 throughout the chunk, so such visits are rare,
+            // and tracking the flag through the eight branches costs more scalar
+            // instructions per visit than their epilogues of zeros)
             if constexpr (SPLIT) {
                 // classes 0..15: lane (q, c) = (lane / 16, lane % 16)
                 float* omr = lgs + 16 * LGS_STRIDE;
@@ -1222,9 +1223,11 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 const float lgt = row_sum4(part);
                 x[15] = om * gS16;
                 const float tot = transpose_reduce<16>(x, lane);
-                const int vi = lane >> 2;              // value index held by this lane
-                if ((lane & 3) == 0) atomicAdd(acc + (size_t)k * VP + (vi < 15 ? vi : A_LG + 16), tot);
-                if (lane < 16) atomicAdd(acc + (size_t)k * VP + A_LG + lane, lgt);
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
+                const int vi = ln >> 2;                // value index held by this lane
+                if ((ln & 3) == 0) atomicAdd(acc + (size_t)k * VP + (vi < 15 ? vi : A_LG + 16), tot);
+                if (ln < 16) atomicAdd(acc + (size_t)k * VP + A_LG + ln, lgt);
             } else {
 #pragma unroll
                 for (int c = 0; c < CP; ++c) x[A_LG + c] = om * gS[c];

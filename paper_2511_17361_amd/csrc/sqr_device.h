@@ -142,17 +142,47 @@ __device__ __forceinline__ Pinned<N> pin(cf_ptr r) {
     for (int i = 0; i < N; ++i) asm volatile("" : "+s"(o.v[i]));
     return o;
 }
-// Two groups (a record and the logits) behind one wait.
+// A group of N wave-uniform floats in flight: for 16 < N < 32 the last 16 as
+// one 16-dword tuple.  Loaded element by element, a group's trailing words
+// (used last: r_cull, the last logit) end up in single-dword loads that the
+// scheduler sinks below the wait for the others, so a visit waits twice;
+// inside the tuple they share the load of words used first.
+typedef float f32x16_t __attribute__((ext_vector_type(16), aligned(4)));
+typedef const __attribute__((address_space(4))) f32x16_t* cf16_ptr;
+template <int N>
+struct GroupLoad {
+    static constexpr bool TUPLE = N > 16 && N < 32;
+    static constexpr int H = TUPLE ? N - 16 : N;    // words loaded one by one
+    float head[H];
+    f32x16_t tail;
+    __device__ __forceinline__ void issue(cf_ptr r) {
+#pragma unroll
+        for (int i = 0; i < H; ++i) head[i] = r[i];
+        if constexpr (TUPLE) tail = *(cf16_ptr)(r + H);
+    }
+    __device__ __forceinline__ void pin(float (&v)[N]) {
+        if constexpr (TUPLE) asm volatile("" : "+s"(tail));
+#pragma unroll
+        for (int i = 0; i < H; ++i) asm volatile("" : "+s"(head[i]));
+#pragma unroll
+        for (int i = 0; i < H; ++i) v[i] = head[i];
+        if constexpr (TUPLE) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[H + i] = tail[i];
+        }
+    }
+};
+// Two groups (a record and the logits): every load issued, then one wait.
 template <int N, int M>
 __device__ __forceinline__ void pin2(cf_ptr r, Pinned<N>& a, cf_ptr q, Pinned<M>& b) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) a.v[i] = r[i];
-#pragma unroll
-    for (int i = 0; i < M; ++i) b.v[i] = q[i];
-#pragma unroll
-    for (int i = 0; i < N; ++i) asm volatile("" : "+s"(a.v[i]));
-#pragma unroll
-    for (int i = 0; i < M; ++i) asm volatile("" : "+s"(b.v[i]));
+    GroupLoad<N> ga;
+    GroupLoad<M> gb;
+    ga.issue(r);
+    gb.issue(q);
+    // both tuples in one statement: neither load can sink below the other's wait
+    if constexpr (GroupLoad<N>::TUPLE && GroupLoad<M>::TUPLE) asm volatile("" : "+s"(ga.tail), "+s"(gb.tail));
+    ga.pin(a.v);
+    gb.pin(b.v);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,18 +343,22 @@ __device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
                                                         false, false);
         x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+    const auto sel = [lane](int bit, float hi, float lo) {
+        uint32_t m = 0u - (((uint32_t)lane >> bit) & 1u);
+        asm("" : "+v"(m));
+        return __uint_as_float((__float_as_uint(hi) & m) | (__float_as_uint(lo) & ~m));
+    };
 #pragma unroll
     for (int i = 0; i < h3; ++i) {
         const float lo = x[i] + dpp_f<DPP_ROW_MIRROR>(x[i]);
         const float hi = x[h3 + i] + dpp_f<DPP_ROW_MIRROR>(x[h3 + i]);
-        x[i] = b3 ? hi : lo;
+        x[i] = sel(3, hi, lo);
     }
 #pragma unroll
     for (int i = 0; i < h4; ++i) {
         const float lo = x[i] + dpp_f<DPP_ROW_HALF_MIRROR>(x[i]);
         const float hi = x[h4 + i] + dpp_f<DPP_ROW_HALF_MIRROR>(x[h4 + i]);
-        x[i] = b2 ? hi : lo;
+        x[i] = sel(2, hi, lo);
     }
     if constexpr (VP == 16) {
         const float t = x[0] + dpp_f<DPP_QUAD_SWAP2>(x[0]);
@@ -334,12 +368,12 @@ __device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
         for (int i = 0; i < h5; ++i) {
             const float lo = x[i] + dpp_f<DPP_QUAD_SWAP2>(x[i]);
             const float hi = x[h5 + i] + dpp_f<DPP_QUAD_SWAP2>(x[h5 + i]);
-            x[i] = b1 ? hi : lo;
+            x[i] = sel(1, hi, lo);
         }
         if constexpr (VP == 64) {
             const float lo = x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
             const float hi = x[1] + dpp_f<DPP_QUAD_SWAP1>(x[1]);
-            return b0 ? hi : lo;
+            return sel(0, hi, lo);
         } else {
             return x[0] + dpp_f<DPP_QUAD_SWAP1>(x[0]);
         }
