@@ -650,40 +650,42 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
     float sv[CP];
 #pragma unroll
     for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
-    auto add_pair = [&](int k) {
-        const cf_ptr r = X.rec + (size_t)k * REC;
-        const float p = eval_p(r, cx, cy, cz);
+    auto add_pair = [&](const auto& rr, const auto& lg) {
+        const float p = eval_p(rr, cx, cy, cz);
         if (p != 0.0f) {
-            d = fmaf(p, r[15], d);
-            const cf_ptr lg = X.lgp + (size_t)k * CP;
+            d = fmaf(p, rr[15], d);
 #pragma unroll
             for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
         }
     };
-    uint64_t m = wave_ballot(act);
-    if (m != 0 && bm) {
-        while (m) {
-            const int l = __builtin_ctzll(m);
-            m &= m - 1;
-            const int f0 = readlane_i(f, l);
-            const int n0 = clamp_list(f0, readlane_i(n, l), X.cap);
-            for (int e = lane; e < n0; e += 64) {
-                const int k = X.ids[f0 + e];
-                if ((unsigned)k < (unsigned)X.n) atomicOr(&bm[k >> 5], 1u << (k & 31));
-            }
+    if (wave_ballot(act) != 0 && bm) {
+        // every lane marks its own voxel's list (the lists' loads in flight
+        // together rather than one list after another)
+        const int n0 = act ? clamp_list(f, n, X.cap) : 0;
+        for (int e = 0; e < n0; e += 4) {
+            int k[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) k[i] = e + i < n0 ? X.ids[f + e + i] : -1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if ((unsigned)k[i] < (unsigned)X.n) atomicOr(&bm[k[i] >> 5], 1u << (k[i] & 31));
         }
         wave_lds_sync();
+        // the record (with its per-axis box) and the logits of each primitive
+        // of the union, loaded together behind one wait
         for_each_marked<true>(bm, nw, lane, [&](int k) {
-            const cf_ptr r = X.rec + (size_t)k * REC;
-            const bool mem = act && in_range(ix, __float_as_int(r[22])) && in_range(iy, __float_as_int(r[23])) &&
-                             in_range(iz, __float_as_int(r[24]));
-            if (mem) add_pair(k);
+            Pinned<25> rr;
+            Pinned<CP> lg;
+            pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+            const bool mem = act && in_range(ix, __float_as_int(rr[22])) && in_range(iy, __float_as_int(rr[23])) &&
+                             in_range(iz, __float_as_int(rr[24]));
+            if (mem) add_pair(rr, lg);
         });
     } else if (act) {
         const int n0 = clamp_list(f, n, X.cap);
         for (int e = 0; e < n0; ++e) {
             const int k = P.ids[S.ids_base + f + e];
-            if ((unsigned)k < (unsigned)X.n) add_pair(k);
+            if ((unsigned)k < (unsigned)X.n) add_pair(X.rec + (size_t)k * REC, X.lgp + (size_t)k * CP);
         }
     }
     if (valid) {
