@@ -1088,30 +1088,28 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             for (int jj = 0; jj < KC; ++jj) { mem[jj] = in_box(pv[jj], glo, hig); anym |= mem[jj]; }
             if (wave_ballot(anym) == 0) return;
             const float sig = rr[15];
-            float pj[KC];     // p of this lane's samples (0: not listed or culled)
+            // gamma up front: the sums are then updated inside each sample's
+            // branch, and a culled pair costs no default value of p
+            const float gam = gamma_of(lg);
             bool hit = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
-                pj[jj] = 0.0f;
                 if (mem[jj]) {
                     if (STATS) { st[1] += 1; if (pair_kept(r, sx[jj], sy[jj], sz[jj])) st[2] += 1; }
-                    const float p = eval_p(rr, sx[jj], sy[jj], sz[jj]);
-                    // (with p = 0 the sum keeps its bits, as in the forward, which skips)
-                    a[jj] = fmaf(p, sig, a[jj]);
-                    pj[jj] = p;
-                    hit |= p != 0.0f;
+                    float p;
+                    if (eval_p_kept(rr, sx[jj], sy[jj], sz[jj], p)) {
+                        // (with p = 0 the sums keep their bits, as in the forward, which skips)
+                        a[jj] = fmaf(p, sig, a[jj]);
+                        G[jj] = fmaf(p, gam, G[jj]);
+                        hit |= p != 0.0f;
+                    }
                 }
             }
             if (wave_ballot(hit) == 0) {
                 // p = 0 for every lane and sample: the adjoint of k is 0 in this
                 // chunk, so pass 2 need not visit it
                 if (lane == 0) bm[k >> 5] &= ~(1u << (k & 31));
-                return;
             }
-            // G_j += p gamma_k, only for primitives that count
-            const float gam = gamma_of(lg);
-#pragma unroll
-            for (int jj = 0; jj < KC; ++jj) G[jj] = fmaf(pj[jj], gam, G[jj]);
         });
 
         // ---- compositing and its adjoint (per lane) -------------------------

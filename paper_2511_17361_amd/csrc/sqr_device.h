@@ -264,23 +264,28 @@ __device__ __forceinline__ bool pair_kept(cf_ptr rec, float x, float y, float z)
 // exponent, so p = 2^-(Bs + Zs) takes no multiply.  The forward, the
 // backward's recompute and the voxelisation all call this, so they agree bit
 // for bit.
+// eval_p_kept: false for a culled pair (p untouched), else p.
 template <typename RecT>
-__device__ __forceinline__ float eval_p(const RecT& rec, float x, float y, float z) {
+__device__ __forceinline__ bool eval_p_kept(const RecT& rec, float x, float y, float z, float& p) {
     const float dx = x - rec[0], dy = y - rec[1], dz = z - rec[2];
     const float u = fmaf(rec[3], dx, fmaf(rec[4], dy, rec[5] * dz));
     const float v = fmaf(rec[6], dx, fmaf(rec[7], dy, rec[8] * dz));
     const float w = fmaf(rec[9], dx, fmaf(rec[10], dy, rec[11] * dz));
     const float au = fabsf(u), av = fabsf(v), aw = fabsf(w);
     const float mx = fmaxf(fmaxf(au, av), aw);
+    if (!(mx < rec[16])) return false;
+    const float a = rec[12], b = rec[13], ee = rec[14];
+    const float X = hw_exp2(a * hw_log2(au));
+    const float Y = hw_exp2(a * hw_log2(av));
+    const float Zs = hw_exp2(fmaf(b, hw_log2(aw), L2_LOG2E));
+    const float Bs = hw_exp2(fmaf(ee, hw_log2(X + Y), L2_LOG2E));
+    p = hw_exp2(-(Bs + Zs));
+    return true;
+}
+template <typename RecT>
+__device__ __forceinline__ float eval_p(const RecT& rec, float x, float y, float z) {
     float p = 0.0f;
-    if (mx < rec[16]) {
-        const float a = rec[12], b = rec[13], ee = rec[14];
-        const float X = hw_exp2(a * hw_log2(au));
-        const float Y = hw_exp2(a * hw_log2(av));
-        const float Zs = hw_exp2(fmaf(b, hw_log2(aw), L2_LOG2E));
-        const float Bs = hw_exp2(fmaf(ee, hw_log2(X + Y), L2_LOG2E));
-        p = hw_exp2(-(Bs + Zs));
-    }
+    eval_p_kept(rec, x, y, z, p);
     return p;
 }
 
