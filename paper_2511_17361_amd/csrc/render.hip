@@ -961,7 +961,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(Ctx P) {
 // rows are then added with two lane swaps.  Only the 15 geometric sums and
 // class 16 go through the reduction (16 values instead of 32).
 constexpr int LGS_STRIDE = 68;                     // floats per class row (bank-spread, 16-byte aligned)
-constexpr int LGS_FLOATS = 16 * LGS_STRIDE + 64;   // g_S rows + the om row
+constexpr int LGS_ZERO = 16 * LGS_STRIDE + 64;     // 16 zeros after the g_S rows and the om row
+constexpr int LGS_FLOATS = LGS_ZERO + 16;
 template <int CP> struct SplitLogits { static constexpr bool on = CP == 17; };
 
 template <int CP, int KC, bool STATS>
@@ -1161,18 +1162,20 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             const float sig = rr[15];
             constexpr int VR = SPLIT ? 16 : VP;     // values reduced across the wave
             float x[VR];
-            // At C = 17 the 16 sums are zeroed through an opaque move: a plain 0
-            // is rematerialised after the first sample's evaluation, a second
-            // set of 16 moves per (chunk, primitive).  The wider rows of the
-            // other class counts would hold too many registers that way.
+            // At C = 17 the 16 sums start from four 16-byte LDS reads of a block
+            // of zeros (no vector ALU instruction).  The block's address is made
+            // opaque per visit: a hoisted read would be copied into the sums with
+            // 16 moves.  The wider rows of the other class counts are cleared
+            // with moves.
             if constexpr (SPLIT) {
-                // pairs of sums cleared by one 64-bit move each
+                typedef float f32x4_t __attribute__((ext_vector_type(4)));
+                typedef const __attribute__((address_space(3))) f32x4_t* lds_f4;
+                lds_f4 z4 = (lds_f4)(lgs + LGS_ZERO);
+                asm volatile("" : "+v"(z4));
 #pragma unroll
-                for (int i = 0; i < VR; i += 2) {
-                    uint64_t z2;
-                    asm volatile("v_mov_b64 %0, 0" : "=v"(z2));
-                    x[i] = __uint_as_float((uint32_t)z2);
-                    x[i + 1] = __uint_as_float((uint32_t)(z2 >> 32));
+                for (int i = 0; i < VR / 4; ++i) {
+                    const f32x4_t z = z4[i];
+                    x[4 * i] = z[0]; x[4 * i + 1] = z[1]; x[4 * i + 2] = z[2]; x[4 * i + 3] = z[3];
                 }
             } else {
 #pragma unroll
@@ -1254,6 +1257,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BWD_WPE(CP,
                  (size_t)wave * LGS_FLOATS;
     // one clear per wave: every chunk's second pass clears the words it reads
     for (int w = (int)(threadIdx.x & 63); w < P.bitmap_words; w += 64) bm[w] = 0u;
+    if constexpr (SplitLogits<CP>::on)
+        if ((threadIdx.x & 63) < 16) lgs[LGS_ZERO + (threadIdx.x & 63)] = 0.0f;
     wave_lds_sync();
     for_each_tile<PERSIST>(P, [&](int t, const Ctx& Q) {
         const int s = find_scene(Q.desc, t);
