@@ -998,6 +998,15 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
     // which keeps 16 registers free across the chunk loop; the summation order
     // is the same either way.
     const float gS16 = gS[CP - 1];
+    // lane constants of the pass-2 epilogue (C = 17): the selects of the
+    // transposing reduction, the permute address of lane ^ 32, and each lane's
+    // accumulator entries (the value index lane / 4: entries 0..14, class 16
+    // for 15; and class lane for the 16 class sums)
+    uint32_t m3 = 0u - (((uint32_t)lane >> 3) & 1u), m2 = 0u - (((uint32_t)lane >> 2) & 1u);
+    asm volatile("" : "+v"(m3), "+v"(m2));
+    const int bp32 = (lane ^ 32) << 2;
+    const uint32_t off_tot = (lane >> 2) < 15 ? (uint32_t)(lane >> 2) : (uint32_t)(A_LG + 16);
+    const uint32_t off_lgt = (uint32_t)(A_LG + (lane & 15));
     auto gamma_of = [&](const Pinned<CP>& lg) {
         float gam = 0.0f;
         if constexpr (SPLIT) {
@@ -1223,14 +1232,16 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 wave_lds_sync();
-                const float lgt = row_sum4(part);
+                const float lgt = row_sum4_lds(part, bp32);
                 x[15] = om * gS16;
-                const float tot = transpose_reduce<16>(x, lane);
+                const float tot = transpose_reduce16(x, m3, m2);
+                // (the lane tests are compares per visit: held lane masks would
+                // take scalar registers for the whole walk)
+                float* const ak = acc + (size_t)k * VP;
                 int ln = lane;
                 asm volatile("" : "+v"(ln));
-                const int vi = ln >> 2;                // value index held by this lane
-                if ((ln & 3) == 0) atomicAdd(acc + (size_t)k * VP + (vi < 15 ? vi : A_LG + 16), tot);
-                if (ln < 16) atomicAdd(acc + (size_t)k * VP + A_LG + ln, lgt);
+                if ((ln & 3) == 0) atomicAdd(ak + off_tot, tot);
+                if (ln < 16) atomicAdd(ak + off_lgt, lgt);
             } else {
 #pragma unroll
                 for (int c = 0; c < CP; ++c) x[A_LG + c] = om * gS[c];

@@ -385,6 +385,51 @@ __device__ __forceinline__ float transpose_reduce(float (&x)[VP], int lane) {
     }
 }
 
+// The 16-value transposing reduction with the lane-bit selects given as
+// vector masks computed once by the caller (m3, m2: all ones where lane bit 3,
+// respectively 2, is set), so that no mask is rebuilt or copied per call.
+// Same levels and summation order as transpose_reduce<16>.
+__device__ __forceinline__ float transpose_reduce16(float (&x)[16], uint32_t m3, uint32_t m2) {
+    const auto sel = [](uint32_t m, float hi, float lo) {
+        float r;    // one bitfield insert: (hi & m) | (lo & ~m)
+        asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(hi), "v"(lo));
+        return r;
+    };
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[i]), __float_as_uint(x[8 + i]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x[i]), __float_as_uint(x[4 + i]), false, false);
+        x[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float lo = x[i] + dpp_f<DPP_ROW_MIRROR>(x[i]);
+        const float hi = x[2 + i] + dpp_f<DPP_ROW_MIRROR>(x[2 + i]);
+        x[i] = sel(m3, hi, lo);
+    }
+    {
+        const float lo = x[0] + dpp_f<DPP_ROW_HALF_MIRROR>(x[0]);
+        const float hi = x[1] + dpp_f<DPP_ROW_HALF_MIRROR>(x[1]);
+        x[0] = sel(m2, hi, lo);
+    }
+    const float t = x[0] + dpp_f<DPP_QUAD_SWAP2>(x[0]);
+    return t + dpp_f<DPP_QUAD_SWAP1>(t);
+}
+
+// Sum of v over the four 16-lane rows, through the LDS crossbar (no vector ALU
+// move or swap): a swizzle that exchanges 16-lane halves of each 32-lane group,
+// then a permute across the 32-lane halves (bp32: this lane's byte address of
+// lane ^ 32).  Every lane gets the total of its position in the row; the sum
+// is (v_l + v_l^16) + (v_l^32 + v_l^48).
+__device__ __forceinline__ float row_sum4_lds(float v, int bp32) {
+    const float s = v + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+    return s + __int_as_float(__builtin_amdgcn_ds_bpermute(bp32, __float_as_int(s)));
+}
+
 // Sum of v over the four 16-lane rows: every lane gets the total of its
 // position in the row (v_permlane32_swap, v_permlane16_swap).
 __device__ __forceinline__ float row_sum4(float v) {
