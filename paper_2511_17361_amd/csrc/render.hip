@@ -418,10 +418,12 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
             for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
             if (STATS && act) { ++st_samples; st_pairs += n; }
             // rr, lg: the record and logits of k, wave-uniform, in SGPRs
+            // (a kept pair whose p underflows to 0 leaves the sums' bits as they
+            // are, so only the cull is tested)
             auto add_pair = [&](int k, const auto& rr, const Pinned<CP>& lg) {
-                const float p = eval_p(rr, cur.x, cur.y, cur.z);
                 if (STATS && pair_kept(X.rec + (size_t)k * REC, cur.x, cur.y, cur.z)) ++st_nz;
-                if (p != 0.0f) {
+                float p;
+                if (eval_p_kept(rr, cur.x, cur.y, cur.z, p)) {
                     a = fmaf(p, rr[15], a);
 #pragma unroll
                     for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
@@ -651,8 +653,8 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
 #pragma unroll
     for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
     auto add_pair = [&](const auto& rr, const auto& lg) {
-        const float p = eval_p(rr, cx, cy, cz);
-        if (p != 0.0f) {
+        float p;
+        if (eval_p_kept(rr, cx, cy, cz, p)) {
             d = fmaf(p, rr[15], d);
 #pragma unroll
             for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
