@@ -42,6 +42,9 @@ typedef int32_t sq_status;
 #define SQ_ERR_UNSUPPORTED -4 /* valid request that this library does not implement */
 
 #define SQ_MAX_CLASSES 32     /* largest supported number of semantic classes C */
+#define SQ_MAX_SCENE_PRIMS (1 << 25) /* most primitives in one scene: the kernels address a
+                                      * primitive's record and logits by 32-bit byte offsets
+                                      * from the scene's base; more returns SQ_ERR_UNSUPPORTED */
 
 /* Voxel grid (Sec. 3.3 "Preliminary Construction"; bounds and resolution of
  * Sec. 4.1).  Voxel (ix,iy,iz) covers [lo + i*voxel, lo + (i+1)*voxel) per axis
@@ -86,7 +89,7 @@ typedef struct {
  * need not be unit: the renderer uses r/|r|, Hamilton convention, and maps a
  * point to the local frame as x_S = R(r/|r|) (x - m)), scales [n,3]
  * (s_x,s_y,s_z > 0), eps [n,2] (eps1, eps2 > 0), opacity [n] (sigma),
- * logits [n,C] (c).  1 <= n_classes <= SQ_MAX_CLASSES. */
+ * logits [n,C] (c).  1 <= n_classes <= SQ_MAX_CLASSES, n <= SQ_MAX_SCENE_PRIMS. */
 typedef struct {
     int32_t      n;
     int32_t      n_classes;

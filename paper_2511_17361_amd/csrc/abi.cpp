@@ -168,6 +168,9 @@ sq_status make_plan(const sq_batch* b, int tile_w, Plan& p) {
         if (sc.index_capacity > INT32_MAX)
             return fail(SQ_ERR_UNSUPPORTED, "scene %d: index_capacity %lld exceeds the int32 offsets of V_f", i,
                         (long long)sc.index_capacity);
+        if (sc.n_prims > SQ_MAX_SCENE_PRIMS)
+            return fail(SQ_ERR_UNSUPPORTED, "scene %d: %d primitives exceed SQ_MAX_SCENE_PRIMS = %d", i, sc.n_prims,
+                        SQ_MAX_SCENE_PRIMS);
         if (index_bound(&b->grid, sc.n_prims) > INT32_MAX)
             return fail(SQ_ERR_UNSUPPORTED,
                         "scene %d: %d primitives can need %lld index entries, beyond the int32 offsets of V_f", i,

@@ -312,6 +312,18 @@ struct SceneIndex {
     cf_ptr rec;     // records of the scene's primitives (local id k at rec + k*REC)
     cf_ptr lgp;
     int n;
+    // Record and logit row of primitive k through a 32-bit byte offset (a
+    // scene holds at most 2^25 primitives, so k * 4 * max(REC, CP) fits): the
+    // scalar loads then take the offset in a register beside the scene's base,
+    // one multiply per visit instead of a 64-bit multiply-add.
+    typedef const __attribute__((address_space(4))) char* cb_ptr;
+    __device__ __forceinline__ cf_ptr rec_at(int k) const {
+        return (cf_ptr)((cb_ptr)rec + (uint32_t)k * (uint32_t)(REC * sizeof(float)));
+    }
+    template <int CP>
+    __device__ __forceinline__ cf_ptr lgp_at(int k) const {
+        return (cf_ptr)((cb_ptr)lgp + (uint32_t)k * (uint32_t)(CP * sizeof(float)));
+    }
 };
 
 template <int CP>
@@ -441,7 +453,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                         if ((unsigned)k < (unsigned)X.n) {
                             Pinned<17> rr;
                             Pinned<CP> lg;
-                            pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+                            pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
                             add_pair(k, rr, lg);
                         }
                     }
@@ -467,7 +479,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 for_each_marked<true>(bm, nw, lane, [&](int k) {
                     Pinned<19> rr;
                     Pinned<CP> lg;
-                    pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+                    pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
                     if (in_box(cell, __float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_HIG]))) add_pair(k, rr, lg);
                 });
                 wave_lds_sync();
@@ -487,7 +499,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                             if ((unsigned)k < (unsigned)X.n) {
                                 Pinned<17> rr;
                                 Pinned<CP> lg;
-                                pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+                                pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
                                 add_pair(k, rr, lg);
                             }
                         }
@@ -678,7 +690,7 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
         for_each_marked<true>(bm, nw, lane, [&](int k) {
             Pinned<25> rr;
             Pinned<CP> lg;
-            pin2(X.rec + (size_t)k * REC, rr, X.lgp + (size_t)k * CP, lg);
+            pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
             const bool mem = act && in_range(ix, __float_as_int(rr[22])) && in_range(iy, __float_as_int(rr[23])) &&
                              in_range(iz, __float_as_int(rr[24]));
             if (mem) add_pair(rr, lg);
@@ -687,7 +699,7 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
         const int n0 = clamp_list(f, n, X.cap);
         for (int e = 0; e < n0; ++e) {
             const int k = P.ids[S.ids_base + f + e];
-            if ((unsigned)k < (unsigned)X.n) add_pair(X.rec + (size_t)k * REC, X.lgp + (size_t)k * CP);
+            if ((unsigned)k < (unsigned)X.n) add_pair(X.rec_at(k), X.template lgp_at<CP>(k));
         }
     }
     if (valid) {
@@ -1089,10 +1101,10 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
 #pragma unroll
         for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
         for_each_marked(bm, nw, lane, [&](int k) {
-            const cf_ptr r = X.rec + (size_t)k * REC;
+            const cf_ptr r = X.rec_at(k);
             Pinned<19> rr;
             Pinned<CP> lg;
-            pin2(r, rr, X.lgp + (size_t)k * CP, lg);
+            pin2(r, rr, X.template lgp_at<CP>(k), lg);
             const uint32_t glo = __float_as_uint(rr[R_GLO]), hig = __float_as_uint(rr[R_HIG]);
             bool mem[KC];
             bool anym = false;
@@ -1159,10 +1171,10 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         // ---- pass 2: per-primitive adjoint over the union -------------------
         wave_lds_sync();
         for_each_marked<true>(bm, nw, lane, [&](int k) {
-            const cf_ptr r = X.rec + (size_t)k * REC;
+            const cf_ptr r = X.rec_at(k);
             Pinned<22> rr;
             Pinned<CP> lg;
-            pin2(r, rr, X.lgp + (size_t)k * CP, lg);
+            pin2(r, rr, X.template lgp_at<CP>(k), lg);
             const uint32_t glo = __float_as_uint(rr[R_GLO]), hig = __float_as_uint(rr[R_HIG]);
             bool mem[KC];
             bool anym = false;

@@ -335,6 +335,34 @@ def test_index_offsets_must_fit_int32():
                               None) == L.SQ_ERR_UNSUPPORTED
 
 
+def test_scene_primitive_count_is_bounded_for_32_bit_record_offsets():
+    """The kernels reach primitive k's record and logits through a 32-bit byte
+    offset from the scene's base, so a scene of more than SQ_MAX_SCENE_PRIMS
+    primitives is refused before any launch, also where the index bound would
+    still fit (one voxel per primitive)."""
+    lib = L.load()
+    assert L.SQ_MAX_SCENE_PRIMS * 32 * 4 <= 2 ** 32     # widest logit row: 32 classes
+    assert L.SQ_MAX_SCENE_PRIMS * 28 * 4 <= 2 ** 32     # record row
+    b, io = _batch(), _batch_io()
+    b.grid = _grid(dims=(1, 1, 1), nv=1)
+    b.scenes[0].n_prims = L.SQ_MAX_SCENE_PRIMS + 1
+    assert lib.sq_index_capacity_bound(ct.byref(b.grid), L.SQ_MAX_SCENE_PRIMS + 1) <= 2 ** 31 - 1
+    t = L.SqTuning(8, 4, 0, 0, 4)
+    calls = (lambda: lib.sq_batch_build_index(ct.byref(b), ct.byref(io), 0x100000, 1 << 40, None),
+             lambda: lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 40, None),
+             lambda: lib.sq_batch_render_bwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 40, None),
+             lambda: lib.sq_batch_step(ct.byref(b), ct.byref(io), ct.byref(t), 0x100000, 1 << 40, None))
+    for call in calls:
+        assert call() == L.SQ_ERR_UNSUPPORTED
+        assert "SQ_MAX_SCENE_PRIMS" in lib.sq_last_error().decode()
+    # single-scene calls take the same bound
+    p = _prims()
+    p.n = L.SQ_MAX_SCENE_PRIMS + 1
+    ix = _index()
+    assert lib.sq_build_index(ct.byref(b.grid), ct.byref(p), ct.byref(ix), 0x100000, 1 << 40,
+                              None) == L.SQ_ERR_UNSUPPORTED
+
+
 def test_checkpoint_length_and_chunk_are_checked():
     """ckpt_len must hold ceil(L/K) * rays floats for the call's chunk K, and a
     batched forward writes checkpoints only with a chunk the backward takes."""
