@@ -42,9 +42,12 @@ typedef int32_t sq_status;
 #define SQ_ERR_UNSUPPORTED -4 /* valid request that this library does not implement */
 
 #define SQ_MAX_CLASSES 32     /* largest supported number of semantic classes C */
-#define SQ_MAX_SCENE_PRIMS (1 << 25) /* most primitives in one scene: the kernels address a
-                                      * primitive's record and logits by 32-bit byte offsets
-                                      * from the scene's base; more returns SQ_ERR_UNSUPPORTED */
+#define SQ_MAX_SCENE_PRIMS ((1 << 25) - 1) /* most primitives in one scene: the kernels
+                                           * address a primitive's record and logits by
+                                           * 32-bit byte offsets from the scene's base, and
+                                           * a scene's logit rows (at most 128 bytes each)
+                                           * by a 32-bit buffer range; more returns
+                                           * SQ_ERR_UNSUPPORTED */
 
 /* Voxel grid (Sec. 3.3 "Preliminary Construction"; bounds and resolution of
  * Sec. 4.1).  Voxel (ix,iy,iz) covers [lo + i*voxel, lo + (i+1)*voxel) per axis

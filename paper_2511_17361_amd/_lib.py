@@ -18,7 +18,7 @@ SQ_ERR_CAPACITY = -2
 SQ_ERR_HIP = -3
 SQ_ERR_UNSUPPORTED = -4
 SQ_MAX_CLASSES = 32
-SQ_MAX_SCENE_PRIMS = 1 << 25
+SQ_MAX_SCENE_PRIMS = (1 << 25) - 1
 
 EXPORTED = [
     "sq_last_error", "sq_version", "sq_default_tuning", "sq_index_capacity_bound",

@@ -29,6 +29,7 @@
 #include "sqr_launch.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace sqr {
 
@@ -313,7 +314,7 @@ struct SceneIndex {
     cf_ptr lgp;
     int n;
     // Record and logit row of primitive k through a 32-bit byte offset (a
-    // scene holds at most 2^25 primitives, so k * 4 * max(REC, CP) fits): the
+    // scene holds fewer than 2^25 primitives, so k * 4 * max(REC, CP) fits): the
     // scalar loads then take the offset in a register beside the scene's base,
     // one multiply per visit instead of a 64-bit multiply-add.
     typedef const __attribute__((address_space(4))) char* cb_ptr;
@@ -393,11 +394,13 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
     const int nck = CKPT ? (L + K - 1) / K : 0;
     float* ckpt = CKPT ? P.ckpt + (int64_t)nck * S.ray_off + lane_lray(rl, S) : nullptr;
 
+    using CS = ClassSums<CP>;
+    const LogitRows<CP> LR(X.lgp, X.n, lane);
+
     float T = rl.valid ? 1.0f : 0.0f;
     float D = 0.0f;
-    float Sv[CP];
-#pragma unroll
-    for (int c = 0; c < CP; ++c) Sv[c] = 0.0f;
+    CS Sv;
+    Sv.zero();
     bool alive = rl.valid;
     int64_t st_samples = 0, st_pairs = 0, st_nz = 0;
 
@@ -425,21 +428,35 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
             // Eq. eq:alpha_sem_sq: a = sum_k p_k sigma_k and s = sum_k p_k c_k over
             // the lane's own list, ascending id
             float a = 0.0f;
-            float sv[CP];
-#pragma unroll
-            for (int c = 0; c < CP; ++c) sv[c] = 0.0f;
+            CS sv;
+            sv.zero();
             if (STATS && act) { ++st_samples; st_pairs += n; }
-            // rr, lg: the record and logits of k, wave-uniform, in SGPRs
-            // (a kept pair whose p underflows to 0 leaves the sums' bits as they
-            // are, so only the cull is tested)
-            auto add_pair = [&](int k, const auto& rr, const Pinned<CP>& lg) {
-                if (STATS && pair_kept(X.rec + (size_t)k * REC, cur.x, cur.y, cur.z)) ++st_nz;
-                float p;
-                if (eval_p_kept(rr, cur.x, cur.y, cur.z, p)) {
-                    a = fmaf(p, rr[15], a);
+            // rr: the record of k, wave-uniform, in SGPRs; lx: its logits past
+            // the matrix-core groups.  The whole wave runs each visit; lanes
+            // outside it (mine false) add p = 0.  (A kept pair whose p
+            // underflows to 0 leaves the sums' bits as they are, so only the
+            // cull is tested.)
+            auto visit = [&](int k, auto rec_words, auto lane_in) {
+                constexpr int NR = decltype(rec_words)::value;
+                float A[CS::NG][CS::W];
+                LR.load(k, A);
+                Pinned<NR> rr;
+                Pinned<CS::XN> lx;
+                if constexpr (CS::NX > 0) pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k) + 4 * CS::NM, lx);
+                else pin1(X.rec_at(k), rr);
+                float p = 0.0f;
+                if (lane_in(rr)) {
+                    if (STATS && pair_kept(X.rec + (size_t)k * REC, cur.x, cur.y, cur.z)) ++st_nz;
+                    if (eval_p_kept(rr, cur.x, cur.y, cur.z, p)) {
+                        a = fmaf(p, rr[15], a);
 #pragma unroll
-                    for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
+                        for (int c = 0; c < CS::NX; ++c) sv.x[c] = fmaf(p, lx[c], sv.x[c]);
+                    }
                 }
+                // the matrix op reads other lanes' operands, so it runs with the
+                // whole wave (a uniform branch), p = 0 where no pair is kept;
+                // skipped when every p is 0
+                if (wave_ballot(p != 0.0f) != 0) class_mfma<CP>(sv, A, p);
             };
             const int lead = __builtin_ctzll(am);
             const int v_lead = readlane_i(cur.v, lead);
@@ -447,16 +464,10 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 // one voxel for every active lane: walk its list
                 const int f0 = readlane_i(f, lead);
                 const int n0 = clamp_list(f0, readlane_i(n, lead), X.cap);
-                if (act) {
-                    for (int e = 0; e < n0; ++e) {
-                        const int k = X.ids[f0 + e];
-                        if ((unsigned)k < (unsigned)X.n) {
-                            Pinned<17> rr;
-                            Pinned<CP> lg;
-                            pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
-                            add_pair(k, rr, lg);
-                        }
-                    }
+                for (int e = 0; e < n0; ++e) {
+                    const int k = X.ids[f0 + e];
+                    if ((unsigned)k < (unsigned)X.n)
+                        visit(k, std::integral_constant<int, 17>{}, [&](const Pinned<17>&) { return act; });
                 }
             } else if (bm) {
                 // several voxels: mark the union of their lists, then walk it
@@ -477,10 +488,9 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 // the union walk runs only on grids whose cells fit the packed form
                 const uint32_t cell = act ? pack_cell(cur.ix, cur.iy, cur.iz) : PV_DEAD;
                 for_each_marked<true>(bm, nw, lane, [&](int k) {
-                    Pinned<19> rr;
-                    Pinned<CP> lg;
-                    pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
-                    if (in_box(cell, __float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_HIG]))) add_pair(k, rr, lg);
+                    visit(k, std::integral_constant<int, 19>{}, [&](const Pinned<19>& rr) {
+                        return in_box(cell, __float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_HIG]));
+                    });
                 });
                 wave_lds_sync();
             } else {
@@ -493,16 +503,10 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                     const int fg = readlane_i(f, g);
                     const int ng = clamp_list(fg, readlane_i(n, g), X.cap);
                     const bool mine = pend && (cur.v == vg);
-                    if (mine) {
-                        for (int e = 0; e < ng; ++e) {
-                            const int k = X.ids[fg + e];
-                            if ((unsigned)k < (unsigned)X.n) {
-                                Pinned<17> rr;
-                                Pinned<CP> lg;
-                                pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
-                                add_pair(k, rr, lg);
-                            }
-                        }
+                    for (int e = 0; e < ng; ++e) {
+                        const int k = X.ids[fg + e];
+                        if ((unsigned)k < (unsigned)X.n)
+                            visit(k, std::integral_constant<int, 17>{}, [&](const Pinned<17>&) { return mine; });
                     }
                     pend = pend && !mine;
                 }
@@ -511,8 +515,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
             const float alpha = fminf(a, 1.0f);
             const float w = T * alpha;
             D = fmaf(w, cur.t, D);
-#pragma unroll
-            for (int c = 0; c < CP; ++c) Sv[c] = fmaf(w, sv[c], Sv[c]);
+            Sv.add_scaled(w, sv);
             T = T * (1.0f - alpha);
             alive = alive && (T > 0.0f) && (T >= P.mr.kappa);
         }
@@ -529,6 +532,9 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
     if (CKPT && P.tile_stop) P.tile_stop[STOP_HEAD + (int64_t)S.tile_off + tile] = j_stop;
 
     float ce = 0.0f, se = 0.0f;      // this lane's loss terms (LOSS)
+    float Sc[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) Sc[c] = Sv.get(c);
     if (rl.valid) {
         const int64_t ray = lane_ray(rl, S);
         P.depth[ray] = D;
@@ -538,17 +544,17 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
         float* semp = P.sem + base;
 #pragma unroll
         for (int c = 0; c < CP; ++c)
-            if (c < P.C) semp[c * HW] = Sv[c];
+            if (c < P.C) semp[c * HW] = Sc[c];
         if (P.probs || LOSS) {
-            float mx = Sv[0];
+            float mx = Sc[0];
 #pragma unroll
             for (int c = 1; c < CP; ++c)
-                if (c < P.C) mx = fmaxf(mx, Sv[c]);
+                if (c < P.C) mx = fmaxf(mx, Sc[c]);
             float e[CP];
             float sum = 0.0f;
 #pragma unroll
             for (int c = 0; c < CP; ++c) {
-                e[c] = c < P.C ? expf(Sv[c] - mx) : 0.0f;
+                e[c] = c < P.C ? expf(Sc[c] - mx) : 0.0f;
                 sum += e[c];
             }
             const float inv = 1.0f / sum;
@@ -567,7 +573,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 float s_lab = 0.0f;
 #pragma unroll
                 for (int c = 0; c < CP; ++c)
-                    if (c == lab) s_lab = Sv[c];
+                    if (c == lab) s_lab = Sc[c];
                 if (hs) ce = logf(sum) + mx - s_lab;
                 const float ks = hs ? P.lam_s / (float)P.lcount[0] : 0.0f;
                 float* gp = P.gs_out + base;
@@ -1191,7 +1197,6 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             // 16 moves.  The wider rows of the other class counts are cleared
             // with moves.
             if constexpr (SPLIT) {
-                typedef float f32x4_t __attribute__((ext_vector_type(4)));
                 typedef const __attribute__((address_space(3))) f32x4_t* lds_f4;
                 lds_f4 z4 = (lds_f4)(lgs + LGS_ZERO);
                 asm volatile("" : "+v"(z4));

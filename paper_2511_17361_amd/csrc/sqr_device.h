@@ -181,8 +181,115 @@ __device__ __forceinline__ void pin2(cf_ptr r, Pinned<N>& a, cf_ptr q, Pinned<M>
     gb.issue(q);
     // both tuples in one statement: neither load can sink below the other's wait
     if constexpr (GroupLoad<N>::TUPLE && GroupLoad<M>::TUPLE) asm volatile("" : "+s"(ga.tail), "+s"(gb.tail));
+    // a tuple and one word (a record and its last logit): likewise
+    if constexpr (GroupLoad<N>::TUPLE && M == 1) asm volatile("" : "+s"(ga.tail), "+s"(gb.head[0]));
     ga.pin(a.v);
     gb.pin(b.v);
+}
+
+// One group: a record alone.
+template <int N>
+__device__ __forceinline__ void pin1(cf_ptr r, Pinned<N>& a) {
+    GroupLoad<N> ga;
+    ga.issue(r);
+    ga.pin(a.v);
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane class sums s_c += p c_k[c] (Eq. eq:alpha_sem_sq) on the matrix cores
+//
+// The 16-block 4x4x1 f32 MFMA forms, in every group of four lanes 4b..4b+3,
+// D[i][j] += A[i] B[j] with A[i] read from lane 4b+i and B[j] from lane 4b+j,
+// and leaves D[i][j] in register i of lane 4b+j.  With B = p (each lane its
+// own sample's value) and A = four logits of primitive k spread over the four
+// lanes of each group, register i of every lane L gains p_L c_k[class of i]:
+// four classes of the whole wave in one instruction instead of four FMAs.
+// A visit reads k's logit row with one vector load per group of 4W classes:
+// the lane with L % 4 = i reads the W classes that start at 4W G + W i, so
+// register i of accumulator (G, q) holds class 4W G + W i + q.  Classes past
+// the last full group (the 17th of 17) stay on FMAs with a scalar logit.
+// A lane that takes no part in a visit passes p = 0 and adds exact zeros.
+// ---------------------------------------------------------------------------
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+template <int CP>
+struct ClassSums {
+    static constexpr int W = CP >= 16 ? 4 : CP >= 8 ? 2 : 1;   // logits a lane loads per group
+    static constexpr int NG = CP >= 16 ? CP / 16 : 1;          // groups of 4W classes
+    static constexpr int NM = NG * W;                          // accumulators of four classes
+    static constexpr int NX = CP - 4 * NM;                     // classes summed by FMAs
+    static constexpr int XN = NX > 0 ? NX : 1;
+    f32x4_t m[NM];
+    float x[XN];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int j = 0; j < NM; ++j) m[j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < XN; ++c) x[c] = 0.0f;
+    }
+    // class c (a constant once the caller's loop is unrolled)
+    __device__ __forceinline__ float get(int c) const {
+        if (c >= 4 * NM) return x[c - 4 * NM];
+        const int r = c % (4 * W);
+        return m[(c / (4 * W)) * W + r % W][r / W];
+    }
+    // this += w * o, class by class
+    __device__ __forceinline__ void add_scaled(float w, const ClassSums& o) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) m[j][i] = fmaf(w, o.m[j][i], m[j][i]);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) x[c] = fmaf(w, o.x[c], x[c]);
+    }
+};
+
+// The logit rows of one scene seen through a buffer resource: a visit's
+// vector loads take the row's byte offset as their scalar offset.
+template <int CP>
+struct LogitRows {
+    using CS = ClassSums<CP>;
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t voff;      // this lane's byte offset inside a group: 4W (L % 4)
+    __device__ __forceinline__ LogitRows(cf_ptr lgp, int n, int lane) {
+        const uint64_t bytes = (uint64_t)n * CP * sizeof(float);
+        rs = __builtin_amdgcn_make_buffer_rsrc((void*)(const float*)lgp, 0, (int)(uint32_t)(bytes < 0xFFFFFFFFull ? bytes : 0xFFFFFFFFull),
+                                               0x00020000);
+        voff = (uint32_t)(lane & 3) * CS::W * sizeof(float);
+    }
+    // the groups of primitive k's row, A[G][q] = class 4W G + W (L % 4) + q
+    __device__ __forceinline__ void load(int k, float (&A)[CS::NG][CS::W]) const {
+        const int row = k * (int)(CP * sizeof(float));
+#pragma unroll
+        for (int G = 0; G < CS::NG; ++G) {
+            const int so = row + G * 4 * CS::W * (int)sizeof(float);
+            if constexpr (CS::W == 4) {
+                const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, so, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) A[G][q] = __uint_as_float(v[q]);
+            } else if constexpr (CS::W == 2) {
+                const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, so, 0);
+                A[G][0] = __uint_as_float(v[0]);
+                A[G][1] = __uint_as_float(v[1]);
+            } else {
+                A[G][0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, so, 0));
+            }
+        }
+    }
+};
+
+// s += p * c_k over the wave (every lane active; p = 0 where a lane adds nothing)
+template <int CP>
+__device__ __forceinline__ void class_mfma(ClassSums<CP>& s, const float (&A)[ClassSums<CP>::NG][ClassSums<CP>::W],
+                                           float p) {
+    using CS = ClassSums<CP>;
+#pragma unroll
+    for (int G = 0; G < CS::NG; ++G)
+#pragma unroll
+        for (int q = 0; q < CS::W; ++q)
+            s.m[G * CS::W + q] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[G][q], p, s.m[G * CS::W + q], 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------

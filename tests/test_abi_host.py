@@ -337,12 +337,13 @@ def test_index_offsets_must_fit_int32():
 
 def test_scene_primitive_count_is_bounded_for_32_bit_record_offsets():
     """The kernels reach primitive k's record and logits through a 32-bit byte
-    offset from the scene's base, so a scene of more than SQ_MAX_SCENE_PRIMS
+    offset from the scene's base, and the scene's logit rows through a buffer
+    range of at most 2^32 - 1 bytes, so a scene of more than SQ_MAX_SCENE_PRIMS
     primitives is refused before any launch, also where the index bound would
     still fit (one voxel per primitive)."""
     lib = L.load()
-    assert L.SQ_MAX_SCENE_PRIMS * 32 * 4 <= 2 ** 32     # widest logit row: 32 classes
-    assert L.SQ_MAX_SCENE_PRIMS * 28 * 4 <= 2 ** 32     # record row
+    assert L.SQ_MAX_SCENE_PRIMS * 32 * 4 <= 2 ** 32 - 1     # widest logit rows: 32 classes
+    assert L.SQ_MAX_SCENE_PRIMS * 28 * 4 <= 2 ** 32 - 1     # records
     b, io = _batch(), _batch_io()
     b.grid = _grid(dims=(1, 1, 1), nv=1)
     b.scenes[0].n_prims = L.SQ_MAX_SCENE_PRIMS + 1

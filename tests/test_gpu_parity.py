@@ -178,16 +178,18 @@ def test_fwd_paper_render_setting_sampled_rays():
     _fwd_case(sc, ray_ids=ids, what="paper setting")
 
 
-def test_fwd_bitmap_union_walk_equals_voxel_group_walk():
+@pytest.mark.parametrize("C", [5, 17])
+def test_fwd_bitmap_union_walk_equals_voxel_group_walk(C):
     """140k primitives: with one wave per block the per-wave union bitmap fits
     the LDS budget, with four it does not and mixed-voxel samples walk one
     voxel group at a time.  Both give each lane its own list in ascending id,
-    so the outputs agree bit for bit; sampled rays are checked against the
-    oracle."""
-    sc = random_scene(26, n=140_000, n_classes=5, nv=1, width=64, height=48, n_samples=40, opacity_hi=0.5,
+    so the outputs agree bit for bit (the matrix-core class sums round as one
+    FMA per pair, and lanes outside a visit add exact zeros); sampled rays are
+    checked against the oracle."""
+    sc = random_scene(26, n=140_000, n_classes=C, nv=1, width=64, height=48, n_samples=40, opacity_hi=0.5,
                       dims=(32, 32, 16), voxel=0.25, lo=(-4.0, -4.0, -2.0), scale_lo=0.03, scale_hi=0.12,
                       t_far=7.0)
-    _say("fwd 140k prims, union (wpb 1) vs voxel groups (wpb 4)")
+    _say("fwd 140k prims, union (wpb 1) vs voxel groups (wpb 4), C", C)
     a, _ = H.run_fwd(sc, ckpt_every=4, tuning=api.Tuning(8, 1))
     b, _ = H.run_fwd(sc, ckpt_every=4, tuning=api.Tuning(8, 4))
     for k in ("depth", "sem", "t_final", "ckpt"):
