@@ -307,8 +307,9 @@ size_t sq_voxelise_workspace(const sq_grid* grid, const sq_prims* prims);
  *                 smallest c with the largest sem[c][v] (compared in float32).
  * The paper uses tau = 0.05.  Outputs: density [V] (required), sem [C, V]
  * (nullable, class planes), labels [V] int32 (nullable), V = voxels in the
- * linear order of sq_grid.  Same cull as sq_render_fwd.  Deterministic: each
- * voxel sums its own list in ascending id. */
+ * linear order of sq_grid.  Same cull as sq_render_fwd.  Deterministic: four
+ * partial sums per voxel, each over a fixed part of the voxel's list in
+ * ascending id, added in a fixed order. */
 sq_status sq_voxelise(const sq_grid* grid, const sq_index* idx, const sq_prims* prims, float tau,
                       float* density, float* sem, int32_t* labels,
                       void* ws, size_t ws_bytes, hipStream_t stream);

@@ -629,28 +629,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP,
 // ---------------------------------------------------------------------------
 // Voxelisation (Supplement "SuperQuadric Voxelisation", Eq. eq:voxelisation)
 //
-// One wavefront per 4x4x4 block of voxels of one scene (blockIdx.y), one lane
-// per voxel.  The wave marks the union of its voxels' lists in its LDS bitmap
-// and walks it in ascending id; each lane takes the primitives whose box holds
-// its voxel -- its own list, in its own order -- and evaluates p_o at its
-// float32 voxel centre:  v_d = sum p sigma,  v_s = sum p c.  The label is the
-// first class maximising v_s, or C ("free") where v_d < tau.  Without a
-// bitmap (LDS budget exceeded) each lane walks its own list.
+// One workgroup of VOX_WAVES wavefronts per 4x4x4 block of voxels of one scene
+// (blockIdx.y); in every wave one lane per voxel.  The waves mark the union of
+// the block's lists in a shared LDS bitmap (wave w marks list entries w, w +
+// VOX_WAVES, ...), then wave w walks the bitmap words w, w + VOX_WAVES, ... in
+// ascending id; each lane takes the primitives whose box holds its voxel and
+// evaluates p_o at its float32 voxel centre into partial sums
+// v_d = sum p sigma, v_s = sum p c.  Wave 0 adds the other waves' partials in
+// wave order (a fixed order: the result does not depend on scheduling).  The
+// label is the first class maximising v_s, or C ("free") where v_d < tau.
+// Without a bitmap (LDS budget exceeded) each lane walks its own list, wave w
+// again taking entries w, w + VOX_WAVES, ...  Splitting a block over several
+// waves shortens the dense blocks: a block's union runs to hundreds of
+// primitives, visited one after another.
 // ---------------------------------------------------------------------------
+constexpr int VOX_WAVES = 4;
+// LDS of a voxelisation workgroup: the bitmap, then the partial sums of waves
+// 1 .. VOX_WAVES-1 ([wave][CP + 1][64]).
+static size_t vox_lds_bytes(int words, int CP) {
+    return (size_t)words * sizeof(uint32_t) + (size_t)(VOX_WAVES - 1) * (CP + 1) * 64 * sizeof(float);
+}
+
 template <int CP>
-__global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
-    extern __shared__ uint32_t bm_all[];
+__global__ __launch_bounds__(64 * VOX_WAVES) void k_voxelise(Ctx P) {
+    extern __shared__ uint32_t lds_all[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint32_t* bm = nullptr;
-    if (P.bitmap_words > 0) {
-        bm = bm_all + (size_t)wave * P.bitmap_words;
-        for (int w = lane; w < P.bitmap_words; w += 64) bm[w] = 0u;
-        wave_lds_sync();
-    }
+    uint32_t* bm = P.bitmap_words > 0 ? lds_all : nullptr;
+    float* part = reinterpret_cast<float*>(lds_all + P.bitmap_words);
+    for (int w = threadIdx.x; w < P.bitmap_words; w += 64 * VOX_WAVES) lds_all[w] = 0u;
+    __syncthreads();
     const int nbx = (P.g.X + 3) >> 2, nby = (P.g.Y + 3) >> 2, nbz = (P.g.Z + 3) >> 2;
-    const int blk = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (int)(blockDim.x >> 6) + wave);
-    if (blk >= nbx * nby * nbz) return;
+    const int blk = blockIdx.x;     // the grid holds exactly nbx * nby * nbz blocks
     const int s = blockIdx.y;
     const SceneDev& S = P.desc->s[s];
     const SceneIndex X = scene_index<CP>(P, s, S);
@@ -678,35 +688,66 @@ __global__ __launch_bounds__(256) void k_voxelise(Ctx P) {
             for (int c = 0; c < CP; ++c) sv[c] = fmaf(p, lg[c], sv[c]);
         }
     };
-    if (wave_ballot(act) != 0 && bm) {
-        // every lane marks its own voxel's list (the lists' loads in flight
-        // together rather than one list after another)
-        const int n0 = act ? clamp_list(f, n, X.cap) : 0;
-        for (int e = 0; e < n0; e += 4) {
-            int k[4];
+    const int n0 = act ? clamp_list(f, n, X.cap) : 0;
+    if (bm) {
+        // marking, sixteen of the lane's entries per round trip (the longest
+        // list sets the marking's length)
+        for (int e = wave; e < n0; e += 16 * VOX_WAVES) {
+            int k[16];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) k[i] = e + i < n0 ? X.ids[f + e + i] : -1;
+            for (int i = 0; i < 16; ++i) {
+                const int ei = e + i * VOX_WAVES;
+                k[i] = ei < n0 ? X.ids[f + ei] : -1;
+            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 16; ++i)
                 if ((unsigned)k[i] < (unsigned)X.n) atomicOr(&bm[k[i] >> 5], 1u << (k[i] & 31));
         }
-        wave_lds_sync();
-        // the record (with its per-axis box) and the logits of each primitive
-        // of the union, loaded together behind one wait
-        for_each_marked<true>(bm, nw, lane, [&](int k) {
-            Pinned<25> rr;
-            Pinned<CP> lg;
-            pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
-            const bool mem = act && in_range(ix, __float_as_int(rr[22])) && in_range(iy, __float_as_int(rr[23])) &&
-                             in_range(iz, __float_as_int(rr[24]));
-            if (mem) add_pair(rr, lg);
-        });
-    } else if (act) {
-        const int n0 = clamp_list(f, n, X.cap);
-        for (int e = 0; e < n0; ++e) {
+        __syncthreads();
+        // this wave's words of the union, ascending; the record (with its
+        // per-axis box) and the logits of each primitive loaded behind one wait
+        for (int jb = 0; jb * VOX_WAVES < nw; jb += 64) {
+            const int wi = (jb + lane) * VOX_WAVES + wave;
+            const uint32_t word = wi < nw ? bm[wi] : 0u;
+            uint64_t nz = wave_ballot(word != 0u);
+            while (nz) {
+                const int l = __builtin_ctzll(nz);
+                nz &= nz - 1;
+                uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)word, l);
+                const int base = ((jb + l) * VOX_WAVES + wave) << 5;
+                while (wv) {
+                    const int k = base + __builtin_ctz(wv);
+                    wv &= wv - 1;
+                    Pinned<25> rr;
+                    Pinned<CP> lg;
+                    pin2(X.rec_at(k), rr, X.template lgp_at<CP>(k), lg);
+                    const bool mem = act && in_range(ix, __float_as_int(rr[22])) &&
+                                     in_range(iy, __float_as_int(rr[23])) && in_range(iz, __float_as_int(rr[24]));
+                    if (mem) add_pair(rr, lg);
+                }
+            }
+        }
+    } else {
+        for (int e = wave; e < n0; e += VOX_WAVES) {
             const int k = P.ids[S.ids_base + f + e];
             if ((unsigned)k < (unsigned)X.n) add_pair(X.rec_at(k), X.template lgp_at<CP>(k));
         }
+    }
+    // the other waves' partials to wave 0, added in wave order
+    if (wave > 0) {
+        float* pw = part + (size_t)(wave - 1) * (CP + 1) * 64;
+        pw[lane] = d;
+#pragma unroll
+        for (int c = 0; c < CP; ++c) pw[(c + 1) * 64 + lane] = sv[c];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 1; w < VOX_WAVES; ++w) {
+        const float* pw = part + (size_t)(w - 1) * (CP + 1) * 64;
+        d += pw[lane];
+#pragma unroll
+        for (int c = 0; c < CP; ++c) sv[c] += pw[(c + 1) * 64 + lane];
     }
     if (valid) {
         const int64_t nvox = (int64_t)P.g.X * P.g.Y * P.g.Z;
@@ -1868,14 +1909,13 @@ template <int CP>
 static void vox_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, const WsLayout& l, const Ctx& P0,
                     hipStream_t st) {
     prep_records<CP>(d, g, io, l, st);
-    int wpb = 4;
-    while (wpb > 1 && !bitmap_fits(d.max_n, wpb)) wpb /= 2;
     Ctx P = P0;
-    if (!bitmap_fits(d.max_n, wpb)) P.bitmap_words = 0;
-    const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);
+    // one shared bitmap per block, within the LDS budget of a block
+    if (vox_lds_bytes(P.bitmap_words, CP) > 64 * 1024) P.bitmap_words = 0;
+    const size_t shm = vox_lds_bytes(P.bitmap_words, CP);
     const int64_t nblk = (int64_t)((g.X + 3) / 4) * ((g.Y + 3) / 4) * ((g.Z + 3) / 4);
-    const dim3 grid((unsigned)((nblk + wpb - 1) / wpb), (unsigned)d.n_scenes);
-    hipLaunchKernelGGL(k_voxelise<CP>, grid, dim3(64 * wpb), shm, st, P);
+    const dim3 grid((unsigned)nblk, (unsigned)d.n_scenes);
+    hipLaunchKernelGGL(k_voxelise<CP>, grid, dim3(64 * VOX_WAVES), shm, st, P);
 }
 
 hipError_t launch_batch_voxelise(const GridDev& g, const BatchDesc& d, const BatchIO& io, float tau, void* ws,
