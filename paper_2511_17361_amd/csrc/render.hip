@@ -179,19 +179,25 @@ __global__ __launch_bounds__(256) void k_count_labels(int64_t n, int C, const in
 
 // loss[0..2] = (total, L_sem, L_depth) from the per-tile partials, summed in
 // tile order (deterministic).  One block of 256 threads.
-__global__ __launch_bounds__(256) void k_loss_reduce(int tiles, const float* __restrict__ lpart,
-                                                     const int* __restrict__ lcount, float lam_s, float lam_d,
-                                                     float* loss) {
-    __shared__ double red[2][256];
+constexpr int LOSS_THREADS = 1024;
+__global__ __launch_bounds__(LOSS_THREADS) void k_loss_reduce(int tiles, const float* __restrict__ lpart,
+                                                              const int* __restrict__ lcount, float lam_s,
+                                                              float lam_d, float* loss) {
+    __shared__ double red[2][LOSS_THREADS];
+    // each thread its fixed stride of tiles, eight loads in flight; then a
+    // fixed tree: the same order on every run
+    const float2* lp = reinterpret_cast<const float2*>(lpart);
     double a = 0.0, b = 0.0;
-    for (int t = threadIdx.x; t < tiles; t += blockDim.x) {
-        a += (double)lpart[2 * t];
-        b += (double)lpart[2 * t + 1];
+#pragma unroll 8
+    for (int t = threadIdx.x; t < tiles; t += LOSS_THREADS) {
+        const float2 v = lp[t];
+        a += (double)v.x;
+        b += (double)v.y;
     }
     red[0][threadIdx.x] = a;
     red[1][threadIdx.x] = b;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = LOSS_THREADS / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
             red[0][threadIdx.x] += red[0][threadIdx.x + h];
             red[1][threadIdx.x] += red[1][threadIdx.x + h];
@@ -1879,7 +1885,7 @@ static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
                                io.sem_label, io.depth_label, l.lcount);
         }
         fwd_launch<CP, true>(P, t, shm, st);
-        hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, d.total_tiles, (const float*)l.lpart,
+        hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(LOSS_THREADS), 0, st, d.total_tiles, (const float*)l.lpart,
                            (const int*)l.lcount, loss->lambda_sem, loss->lambda_depth, io.loss);
         return;
     }
