@@ -120,9 +120,9 @@ __global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const 
     r[16] = exp2f(0.5f * e1 * log2f(F_CULL));
     int box[3];
     prim_box(g, means + 3 * k, quats + 4 * k, scales + 3 * k, eps + 2 * k, opacity + k, box);
-    uint32_t glo, hig;
-    box_words(box, glo, hig);
-    r[R_GLO] = __uint_as_float(glo); r[R_HIG] = __uint_as_float(hig);
+    uint32_t glo, ghi;
+    box_words(box, glo, ghi);
+    r[R_GLO] = __uint_as_float(glo); r[R_GHI] = __uint_as_float(ghi);
     r[R_AM1] = r[12] - 1.0f; r[R_BM1] = r[13] - 1.0f; r[R_EM1] = r[14] - 1.0f;
     r[22] = __int_as_float(box[0]); r[23] = __int_as_float(box[1]); r[24] = __int_as_float(box[2]);
     r[R_INVS] = is[0]; r[R_INVS + 1] = is[1]; r[R_INVS + 2] = is[2];
@@ -495,7 +495,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                 const uint32_t cell = act ? pack_cell(cur.ix, cur.iy, cur.iz) : PV_DEAD;
                 for_each_marked<true>(bm, nw, lane, [&](int k) {
                     visit(k, std::integral_constant<int, 19>{}, [&](const Pinned<19>& rr) {
-                        return in_box(cell, __float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_HIG]));
+                        return in_box(cell, __float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_GHI]));
                     });
                 });
                 wave_lds_sync();
@@ -1115,11 +1115,13 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         // (the bitmap is clear here: cleared at the start, and pass 2 clears
         // every word it reads)
         float sx[KC], sy[KC], sz[KC];
-        uint32_t pv[KC];     // packed cell of each sample (PV_DEAD: absent)
+        // packed cell of each sample (PV_DEAD: absent), two samples per 64 bits
+        // so that a visit tests them in pairs (in_box2)
+        CellPairs<KC> pv;
         int last_v = -1;
 #pragma unroll
         for (int jj = 0; jj < KC; ++jj) {
-            pv[jj] = PV_DEAD;
+            pv.set(jj, PV_DEAD);
             sx[jj] = sy[jj] = sz[jj] = 0.0f;
             if (j0 + jj <= stop) {
                 const SamplePos sp = pinned_sample(P.g, P.mr.t_near, P.mr.delta, j0 + jj, rl.ox, rl.oy, rl.oz,
@@ -1128,7 +1130,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 int n = 0, f = 0;
                 bool act = (Tc > 0.0f) && (Tc >= kappa) && (sp.v >= 0);
                 if (act) { n = X.counts[sp.v]; f = X.offsets[sp.v]; act = n > 0; }
-                if (act) pv[jj] = pack_cell(sp.ix, sp.iy, sp.iz);
+                if (act) pv.set(jj, pack_cell(sp.ix, sp.iy, sp.iz));
                 bool pend = act;
                 uint64_t m;
                 while ((m = wave_ballot(pend)) != 0) {
@@ -1158,11 +1160,11 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             Pinned<19> rr;
             Pinned<CP> lg;
             pin2(r, rr, X.template lgp_at<CP>(k), lg);
-            const uint32_t glo = __float_as_uint(rr[R_GLO]), hig = __float_as_uint(rr[R_HIG]);
             bool mem[KC];
+            pv.members(__float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_GHI]), mem);
             bool anym = false;
 #pragma unroll
-            for (int jj = 0; jj < KC; ++jj) { mem[jj] = in_box(pv[jj], glo, hig); anym |= mem[jj]; }
+            for (int jj = 0; jj < KC; ++jj) anym |= mem[jj];
             if (wave_ballot(anym) == 0) return;
             const float sig = rr[15];
             // gamma up front: the sums are then updated inside each sample's
@@ -1213,9 +1215,9 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 Q = fmaf(al, Gf, (1.0f - al) * Q);
                 const float da = (a[jj] < 1.0f) ? dal : 0.0f;
                 const float w = Tj[jj] * al;
-                if (STATS && pv[jj] != PV_DEAD) st[0] += 1;
-                if (!(Tj[jj] > 0.0f) || (da == 0.0f && w == 0.0f)) pv[jj] = PV_DEAD;
-                if (STATS && pv[jj] != PV_DEAD) st[3] += 1;
+                if (STATS && pv.get(jj) != PV_DEAD) st[0] += 1;
+                if (!(Tj[jj] > 0.0f) || (da == 0.0f && w == 0.0f)) pv.set(jj, PV_DEAD);
+                if (STATS && pv.get(jj) != PV_DEAD) st[3] += 1;
                 a[jj] = da;     // reuse: dL/da_j
                 G[jj] = w;      // reuse: w_j
             }
@@ -1228,11 +1230,11 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             Pinned<22> rr;
             Pinned<CP> lg;
             pin2(r, rr, X.template lgp_at<CP>(k), lg);
-            const uint32_t glo = __float_as_uint(rr[R_GLO]), hig = __float_as_uint(rr[R_HIG]);
             bool mem[KC];
+            pv.members(__float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_GHI]), mem);
             bool anym = false;
 #pragma unroll
-            for (int jj = 0; jj < KC; ++jj) { mem[jj] = in_box(pv[jj], glo, hig); anym |= mem[jj]; }
+            for (int jj = 0; jj < KC; ++jj) anym |= mem[jj];
             if (wave_ballot(anym) == 0) return;
             const float gam = gamma_of(lg);
             const float sig = rr[15];

@@ -28,7 +28,7 @@ namespace sqr {
 //   [25..27] 1/s
 // The forward walks read [0..18], the adjoint [0..21].
 // ---------------------------------------------------------------------------
-constexpr int R_GLO = 17, R_HIG = 18, R_AM1 = 19, R_BM1 = 20, R_EM1 = 21, R_INVS = 25;
+constexpr int R_GLO = 17, R_GHI = 18, R_AM1 = 19, R_BM1 = 20, R_EM1 = 21, R_INVS = 25;
 constexpr int REC = 28;
 constexpr int EMPTY_BOX = 0x7fff7fff;
 constexpr float F_CULL = 110.0f;          // exp(-110) = 1.7e-48: 0 in float32
@@ -626,22 +626,26 @@ __device__ __forceinline__ bool in_range(int i, int packed) {
 
 // Voxel cells packed into one word, x | y << 11 | z << 22, with a guard bit
 // above each field (bits 10, 21, 31).  The three-axis box test then takes two
-// subtractions and one and-or: for a cell word c with clear guards,
-//   c + (G - lo) keeps a field's guard bit set exactly when c_f >= lo_f,
-//   (hi | G) - c keeps it set exactly when c_f <= hi_f,
-// and no borrow or carry crosses a guard.  Grids up to PV_MAX_XY x PV_MAX_XY x
-// PV_MAX_Z cells fit; PV_DEAD (every field at its maximum, above any cell of
-// such a grid) lies in no box.
+// additions and one three-input bit operation: for a cell word c with clear
+// guards,
+//   c + (G - lo)       keeps a field's guard bit set exactly when c_f >= lo_f,
+//   c + (G - (hi + 1)) sets it exactly when c_f > hi_f,
+// and no carry crosses a guard or leaves the word.  Grids up to PV_MAX_XY x
+// PV_MAX_XY x PV_MAX_Z cells fit; PV_DEAD (every field at its maximum, above any
+// cell of such a grid) lies in no box.  Two cells packed in 64 bits are tested
+// with two 64-bit additions (in_box2): neither half carries into the other.
 constexpr uint32_t PV_GUARDS = (1u << 10) | (1u << 21) | (1u << 31);
+constexpr uint32_t PV_ONES = 1u | (1u << 11) | (1u << 22);
 constexpr int PV_MAX_XY = 1023, PV_MAX_Z = 511;
 constexpr uint32_t PV_DEAD = 0x3ffu | (0x3ffu << 11) | (0x1ffu << 22);
 
 __device__ __forceinline__ uint32_t pack_cell(int ix, int iy, int iz) {
     return (uint32_t)ix | ((uint32_t)iy << 11) | ((uint32_t)iz << 22);
 }
-// The record words of a per-axis box (prim_box's output): G - lo and hi | G.
-// An empty box gets lo above hi in every field, which no cell satisfies.
-__device__ __forceinline__ void box_words(const int box[3], uint32_t& glo, uint32_t& hig) {
+// The record words of a per-axis box (prim_box's output): G - lo and
+// G - (hi + 1).  An empty box gets lo above hi in every field, which no cell
+// satisfies.
+__device__ __forceinline__ void box_words(const int box[3], uint32_t& glo, uint32_t& ghi) {
     int lo[3], hi[3];
     bool empty = false;
     const int cap[3] = {PV_MAX_XY, PV_MAX_XY, PV_MAX_Z};
@@ -653,11 +657,43 @@ __device__ __forceinline__ void box_words(const int box[3], uint32_t& glo, uint3
     const uint32_t plo = empty ? PV_DEAD : pack_cell(lo[0], lo[1], lo[2]);
     const uint32_t phi = empty ? 0u : pack_cell(hi[0], hi[1], hi[2]);
     glo = PV_GUARDS - plo;
-    hig = phi | PV_GUARDS;
+    ghi = PV_GUARDS - (phi + PV_ONES);
 }
-// Cell word c (guards clear) inside the box of record words glo, hig?
-__device__ __forceinline__ bool in_box(uint32_t c, uint32_t glo, uint32_t hig) {
-    return (((c + glo) & (hig - c)) | ~PV_GUARDS) == 0xffffffffu;
+// Guards of a = c + glo all set and of b = c + ghi all clear.
+__device__ __forceinline__ bool box_guards(uint32_t a, uint32_t b) {
+    return (a & ~b & PV_GUARDS) == PV_GUARDS;
 }
+// Cell word c (guards clear) inside the box of record words glo, ghi?
+__device__ __forceinline__ bool in_box(uint32_t c, uint32_t glo, uint32_t ghi) {
+    return box_guards(c + glo, c + ghi);
+}
+// Two cells c2 = c0 | c1 << 32 against one box (glo2 = glo | glo << 32, and
+// likewise ghi2).
+__device__ __forceinline__ void in_box2(uint64_t c2, uint64_t glo2, uint64_t ghi2, bool& m0, bool& m1) {
+    // one 64-bit add each (left to itself the compiler splits them into a
+    // 64-bit multiply-add and a 32-bit add)
+    uint64_t a, b;
+    asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(a) : "v"(c2), "s"(glo2));
+    asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(b) : "v"(c2), "s"(ghi2));
+    m0 = box_guards((uint32_t)a, (uint32_t)b);
+    m1 = box_guards((uint32_t)(a >> 32), (uint32_t)(b >> 32));
+}
+// K packed cells held in pairs (K even); get/set take a constant index once the
+// caller's loop is unrolled.
+template <int K>
+struct CellPairs {
+    uint64_t w[K / 2];
+    __device__ __forceinline__ uint32_t get(int j) const { return (uint32_t)(w[j >> 1] >> (32 * (j & 1))); }
+    __device__ __forceinline__ void set(int j, uint32_t c) {
+        const int sh = 32 * (j & 1);
+        w[j >> 1] = (w[j >> 1] & ~(0xffffffffull << sh)) | ((uint64_t)c << sh);
+    }
+    // mem[j]: cell j inside the box of record words glo, ghi
+    __device__ __forceinline__ void members(uint32_t glo, uint32_t ghi, bool (&mem)[K]) const {
+        const uint64_t glo2 = glo | ((uint64_t)glo << 32), ghi2 = ghi | ((uint64_t)ghi << 32);
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) in_box2(w[i], glo2, ghi2, mem[2 * i], mem[2 * i + 1]);
+    }
+};
 
 }  // namespace sqr
