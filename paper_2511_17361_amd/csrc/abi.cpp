@@ -72,6 +72,7 @@ sqr::GridDev to_dev(const sq_grid* g) {
     d.nv = g->nv;
     d.vs = g->voxel;
     d.theta = g->theta;
+    d.fX = (float)d.X; d.fY = (float)d.Y; d.fZ = (float)d.Z;   // exact: dims are below 2^24
     return d;
 }
 

@@ -59,6 +59,8 @@ struct GridDev {
     int nv;
     float vs;           // voxel edge length
     float theta;        // influence threshold of the index (0: the N_v cube)
+    float fX, fY, fZ;   // X, Y, Z as floats (exact), set on the host: uniform
+                        // operands rather than per-lane conversions
 };
 
 struct SamplePos {
@@ -79,8 +81,7 @@ __device__ __forceinline__ SamplePos pinned_sample(const GridDev& g, float t_nea
     const float qx = (s.x - g.lox) * g.inv;
     const float qy = (s.y - g.loy) * g.inv;
     const float qz = (s.z - g.loz) * g.inv;
-    const bool in = (qx >= 0.0f) & (qx < (float)g.X) & (qy >= 0.0f) & (qy < (float)g.Y) &
-                    (qz >= 0.0f) & (qz < (float)g.Z);
+    const bool in = (qx >= 0.0f) & (qx < g.fX) & (qy >= 0.0f) & (qy < g.fY) & (qz >= 0.0f) & (qz < g.fZ);
     // q >= 0 here, so truncation is floor
     s.ix = in ? (int)qx : 0;
     s.iy = in ? (int)qy : 0;
@@ -100,9 +101,9 @@ __device__ __forceinline__ bool left_grid(const GridDev& g, const SamplePos& s, 
     const float qx = (s.x - g.lox) * g.inv;
     const float qy = (s.y - g.loy) * g.inv;
     const float qz = (s.z - g.loz) * g.inv;
-    return ((qx >= (float)g.X) & (dx >= 0.0f)) | ((qx < 0.0f) & (dx <= 0.0f)) |
-           ((qy >= (float)g.Y) & (dy >= 0.0f)) | ((qy < 0.0f) & (dy <= 0.0f)) |
-           ((qz >= (float)g.Z) & (dz >= 0.0f)) | ((qz < 0.0f) & (dz <= 0.0f));
+    return ((qx >= g.fX) & (dx >= 0.0f)) | ((qx < 0.0f) & (dx <= 0.0f)) |
+           ((qy >= g.fY) & (dy >= 0.0f)) | ((qy < 0.0f) & (dy <= 0.0f)) |
+           ((qz >= g.fZ) & (dz >= 0.0f)) | ((qz < 0.0f) & (dz <= 0.0f));
 }
 
 // Centre of voxel i along one axis in float32, fl(lo + fl(fl(i + 0.5) * voxel))
