@@ -262,10 +262,11 @@ struct LogitRows {
     }
     // the groups of primitive k's row, A[G][q] = class 4W G + W (L % 4) + q
     __device__ __forceinline__ void load(int k, float (&A)[CS::NG][CS::W]) const {
-        const int row = k * (int)(CP * sizeof(float));
+        // (unsigned: a row's byte offset reaches 2^32 - 128 at the largest scenes)
+        const uint32_t row = (uint32_t)k * (uint32_t)(CP * sizeof(float));
 #pragma unroll
         for (int G = 0; G < CS::NG; ++G) {
-            const int so = row + G * 4 * CS::W * (int)sizeof(float);
+            const int so = (int)(row + (uint32_t)(G * 4 * CS::W * sizeof(float)));
             if constexpr (CS::W == 4) {
                 const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, so, 0);
 #pragma unroll
