@@ -458,6 +458,27 @@ sq_status sq_batch_autotune(const sq_batch* batch, const sq_batch_io* io, const 
                             int32_t n_candidates, int32_t reps, int32_t* best_index, float* ms_per_candidate,
                             void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* The autotuner behind a persistent cache (a text file, one line per workload:
+ * its key, " => ", then tile_w waves_per_block bwd_mode persistent chunk).
+ * The batch and the candidates are validated first, as for sq_batch_autotune.
+ * Then a line of cache_path whose key equals this batch's (sq_batch_tuning_key)
+ * gives *best with no launch and *from_cache = 1; otherwise the candidates
+ * are timed by sq_batch_autotune, the fastest is returned with *from_cache = 0
+ * and appended to the file (a file that cannot be written leaves the result
+ * valid and is reported by sq_last_error only).  A missing file is an empty
+ * cache, a line that does not parse is skipped; cache_path NULL times every
+ * call.  A cached tuning need not be among this call's candidates. */
+sq_status sq_batch_autotune_cached(const sq_batch* batch, const sq_batch_io* io, const sq_tuning* candidates,
+                                   int32_t n_candidates, int32_t reps, const char* cache_path, sq_tuning* best,
+                                   int32_t* from_cache, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* The cache key of a batch: library version, the current device's
+ * architecture ("nodevice" without one), scene shapes, grid, march and class
+ * count, as one line of text without spaces.  Writes at most n bytes
+ * including the terminating zero; returns the key's length, or -1 for a
+ * NULL batch. */
+int32_t sq_batch_tuning_key(const sq_batch* batch, char* buf, int32_t n);
+
 /* ------------------------------------------------------------------------
  * Allocation-free forward, for callers that cannot allocate device memory:
  * code under hipGraph capture, tight serving loops, harnesses that forbid

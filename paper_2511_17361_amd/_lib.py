@@ -28,6 +28,7 @@ EXPORTED = [
     "sq_voxelise_workspace", "sq_voxelise", "sq_batch_voxelise",
     "sq_render_fwd_loss", "sq_batch_render_fwd_loss", "sq_batch_train_step", "sq_batch_train_graph_create",
     "sq_sq_major_workspace", "sq_render_bwd_sq_major", "sq_batch_tile_stop_len", "sq_render_fwd_noalloc",
+    "sq_batch_autotune_cached", "sq_batch_tuning_key",
 ]
 SQ_NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -155,6 +156,12 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.sq_batch_autotune.restype = ct.c_int32
     lib.sq_batch_autotune.argtypes = [P(SqBatch), P(SqBatchIO), P(SqTuning), ct.c_int32, ct.c_int32,
                                       P(ct.c_int32), P(ct.c_float), ct.c_void_p, ct.c_size_t, ct.c_void_p]
+    lib.sq_batch_autotune_cached.restype = ct.c_int32
+    lib.sq_batch_autotune_cached.argtypes = [P(SqBatch), P(SqBatchIO), P(SqTuning), ct.c_int32, ct.c_int32,
+                                             ct.c_char_p, P(SqTuning), P(ct.c_int32), ct.c_void_p, ct.c_size_t,
+                                             ct.c_void_p]
+    lib.sq_batch_tuning_key.restype = ct.c_int32
+    lib.sq_batch_tuning_key.argtypes = [P(SqBatch), ct.c_char_p, ct.c_int32]
     lib.sq_voxelise_workspace.restype = ct.c_size_t
     lib.sq_voxelise_workspace.argtypes = [P(SqGrid), P(SqPrims)]
     lib.sq_voxelise.restype = ct.c_int32

@@ -8,6 +8,7 @@ workspace with torch, and calls one C entry point.
 from __future__ import annotations
 
 import ctypes as ct
+import os
 import dataclasses
 from dataclasses import dataclass
 from typing import Optional
@@ -644,6 +645,29 @@ class Batch:
         L.check(lib.sq_batch_autotune(ct.byref(self.c_batch), ct.byref(self.io()), arr, n, int(reps),
                                       ct.byref(best), ms, _ptr(self.ws), self.ws.numel(), _stream_handle(stream)))
         return candidates[best.value], list(ms)
+
+    def autotune_cached(self, candidates, cache_path, reps: int = 2, stream=None):
+        """sq_batch_autotune_cached: the tuning stored under this batch's key in
+        cache_path, else the fastest candidate (timed, then appended to the
+        file).  Returns (best Tuning, from_cache)."""
+        lib = L.load()
+        n = len(candidates)
+        arr = (L.SqTuning * n)(*[c.c() for c in candidates])
+        best = L.SqTuning()
+        hit = ct.c_int32(0)
+        path = None if cache_path is None else os.fsencode(cache_path)
+        L.check(lib.sq_batch_autotune_cached(ct.byref(self.c_batch), ct.byref(self.io()), arr, n, int(reps), path,
+                                             ct.byref(best), ct.byref(hit), _ptr(self.ws), self.ws.numel(),
+                                             _stream_handle(stream)))
+        return Tuning(best.tile_w, best.waves_per_block, best.bwd_mode, best.persistent, best.chunk), bool(hit.value)
+
+    def tuning_key(self) -> str:
+        """The autotune cache key of this batch on the current device."""
+        lib = L.load()
+        n = lib.sq_batch_tuning_key(ct.byref(self.c_batch), None, 0)
+        buf = ct.create_string_buffer(n + 1)
+        lib.sq_batch_tuning_key(ct.byref(self.c_batch), buf, n + 1)
+        return buf.value.decode()
 
     # ---- views of one scene's slice of the concatenated outputs ----
     def scene_slices(self, i):

@@ -4,12 +4,14 @@
 // batch of one.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 
 #include "../../include/sqr.h"
 #include "sqr_internal.h"
@@ -191,6 +193,38 @@ sq_status make_plan(const sq_batch* b, int tile_w, Plan& p) {
     p.g = to_dev(&b->grid);
     p.m = b->march;
     return SQ_OK;
+}
+
+// Every autotune candidate checked against the batch before any launch.
+sq_status check_candidates(const sq_batch* b, const sq_batch_io* io, const sq_tuning* candidates, int n_candidates,
+                           int reps, void* ws, size_t ws_bytes);
+
+// The autotune cache key of a batch (one line, no spaces; floats in hex).
+std::string tuning_key(const sq_batch* b) {
+    char arch[128] = "nodevice";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+        for (char* c = arch; *c; ++c)
+            if (*c == ' ' || *c == '|') *c = '_';
+    } else {
+        (void)hipGetLastError();
+    }
+    char t[512];
+    const sq_grid& g = b->grid;
+    const sq_march& m = b->march;
+    std::snprintf(t, sizeof(t), "v%d|%s|C%d|g%dx%dx%d,%a,%a,%a,%a,%d,%a|m%d,%a,%a,%d,%a|S%d", sq_version(), arch,
+                  b->n_classes, g.dims[0], g.dims[1], g.dims[2], g.lo[0], g.lo[1], g.lo[2], g.voxel, g.nv, g.theta,
+                  m.n_samples, m.t_near, m.t_far, m.ckpt_every, m.kappa, b->n_scenes);
+    std::string k = t;
+    const int ns = std::max(0, std::min<int>(b->n_scenes, SQ_MAX_SCENES));
+    for (int i = 0; i < ns; ++i) {
+        const sq_scene& sc = b->scenes[i];
+        std::snprintf(t, sizeof(t), "|%d,%d,%d,%d", sc.n_prims, sc.n_cams, sc.height, sc.width);
+        k += t;
+    }
+    return k;
 }
 
 sq_status check_ws(void* ws, size_t ws_bytes, size_t need) {
@@ -413,6 +447,31 @@ void io_from(const sq_index* idx, const sq_prims* pr, const sq_rays* rays, sq_ba
 }
 
 // Rows of the single-scene checkpoint layout [ceil(L/K), R] (0 without checkpoints).
+sq_status check_candidates(const sq_batch* b, const sq_batch_io* io, const sq_tuning* candidates, int n_candidates,
+                           int reps, void* ws, size_t ws_bytes) {
+    if (!candidates || n_candidates < 1 || reps < 1)
+        return fail(SQ_ERR_INVALID, "need candidates, n_candidates >= 1 and reps >= 1");
+    // an invalid candidate rejects the call before any launch
+    for (int i = 0; i < n_candidates; ++i) {
+        sqr::TuneDev tune;
+        sq_status s;
+        if ((s = tuning_of(&candidates[i], tune))) return s;
+        Plan p;
+        if ((s = make_plan(b, tune.tile_w, p))) return s;
+        if ((s = check_io_render(p, io))) return s;
+        if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
+        const int K = chunk_of(&candidates[i], p.m);
+        if (!chunk_ok(K)) return fail(SQ_ERR_INVALID, "candidate %d: chunk %d", i, K);
+        if (!io->ckpt) return fail(SQ_ERR_INVALID, "autotune times full steps: ckpt is NULL");
+        if ((s = check_ckpt(p, io, K))) return s;
+        if ((s = check_tile_stop(p, io))) return s;
+        if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
+            !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
+            return fail(SQ_ERR_UNSUPPORTED, "candidate %d: primitive-major backward does not apply", i);
+    }
+    return SQ_OK;
+}
+
 int64_t ckpt_rows(const sq_march* m) {
     return m->ckpt_every > 0 ? (m->n_samples + m->ckpt_every - 1) / m->ckpt_every : 0;
 }
@@ -817,26 +876,9 @@ sq_status sq_graph_destroy(sq_graph graph) {
 sq_status sq_batch_autotune(const sq_batch* b, const sq_batch_io* io, const sq_tuning* candidates,
                             int32_t n_candidates, int32_t reps, int32_t* best_index, float* ms_per_candidate,
                             void* ws, size_t ws_bytes, hipStream_t stream) {
-    if (!candidates || n_candidates < 1 || reps < 1 || !best_index)
-        return fail(SQ_ERR_INVALID, "need candidates, n_candidates >= 1, reps >= 1 and best_index");
-    // validate every candidate first: an invalid one rejects the call before any launch
-    for (int i = 0; i < n_candidates; ++i) {
-        sqr::TuneDev tune;
-        sq_status s;
-        if ((s = tuning_of(&candidates[i], tune))) return s;
-        Plan p;
-        if ((s = make_plan(b, tune.tile_w, p))) return s;
-        if ((s = check_io_render(p, io))) return s;
-        if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
-        const int K = chunk_of(&candidates[i], p.m);
-        if (!chunk_ok(K)) return fail(SQ_ERR_INVALID, "candidate %d: chunk %d", i, K);
-        if (!io->ckpt) return fail(SQ_ERR_INVALID, "autotune times full steps: ckpt is NULL");
-        if ((s = check_ckpt(p, io, K))) return s;
-        if ((s = check_tile_stop(p, io))) return s;
-        if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
-            !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
-            return fail(SQ_ERR_UNSUPPORTED, "candidate %d: primitive-major backward does not apply", i);
-    }
+    if (!best_index) return fail(SQ_ERR_INVALID, "best_index is NULL");
+    sq_status st = check_candidates(b, io, candidates, n_candidates, reps, ws, ws_bytes);
+    if (st) return st;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(SQ_ERR_HIP, "hipEventCreate");
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -845,7 +887,6 @@ sq_status sq_batch_autotune(const sq_batch* b, const sq_batch_io* io, const sq_t
     }
     float best = 0.0f;
     int bi = -1;
-    sq_status st = SQ_OK;
     for (int i = 0; i < n_candidates && st == SQ_OK; ++i) {
         st = sq_batch_step(b, io, &candidates[i], ws, ws_bytes, stream);   // warm-up
         if (st) break;
@@ -870,6 +911,65 @@ sq_status sq_batch_autotune(const sq_batch* b, const sq_batch_io* io, const sq_t
     if (st) return st;
     *best_index = bi;
     return ok();
+}
+
+int32_t sq_batch_tuning_key(const sq_batch* b, char* buf, int32_t n) {
+    if (!b) return -1;
+    const std::string k = tuning_key(b);
+    if (buf && n > 0) {
+        const size_t m = std::min<size_t>((size_t)n - 1, k.size());
+        std::memcpy(buf, k.data(), m);
+        buf[m] = '\0';
+    }
+    return (int32_t)k.size();
+}
+
+sq_status sq_batch_autotune_cached(const sq_batch* b, const sq_batch_io* io, const sq_tuning* candidates,
+                                   int32_t n_candidates, int32_t reps, const char* cache_path, sq_tuning* best,
+                                   int32_t* from_cache, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!best) return fail(SQ_ERR_INVALID, "best is NULL");
+    sq_status st = check_candidates(b, io, candidates, n_candidates, reps, ws, ws_bytes);
+    if (st) return st;
+    const std::string key = tuning_key(b);
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char line[4096];
+            bool hit = false;
+            sq_tuning found{};
+            while (std::fgets(line, sizeof(line), f)) {
+                const char* sep = std::strstr(line, " => ");
+                if (!sep || (size_t)(sep - line) != key.size() || std::strncmp(line, key.c_str(), key.size()) != 0)
+                    continue;
+                sq_tuning t{};
+                if (std::sscanf(sep + 4, "%d %d %d %d %d", &t.tile_w, &t.waves_per_block, &t.bwd_mode, &t.persistent,
+                                &t.chunk) != 5)
+                    continue;
+                sqr::TuneDev td;
+                if (tuning_of(&t, td)) continue;    // (a line this library cannot run is skipped)
+                found = t;                          // the last matching line wins
+                hit = true;
+            }
+            std::fclose(f);
+            if (hit) {
+                *best = found;
+                if (from_cache) *from_cache = 1;
+                return ok();
+            }
+        }
+    }
+    int32_t bi = -1;
+    if ((st = sq_batch_autotune(b, io, candidates, n_candidates, reps, &bi, nullptr, ws, ws_bytes, stream))) return st;
+    *best = candidates[bi];
+    if (from_cache) *from_cache = 0;
+    ok();
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f || std::fprintf(f, "%s => %d %d %d %d %d\n", key.c_str(), best->tile_w, best->waves_per_block,
+                               best->bwd_mode, best->persistent, best->chunk) < 0)
+            fail(SQ_ERR_INVALID, "autotune cache %s not written", cache_path);   // reported, result still valid
+        if (f) std::fclose(f);
+    }
+    return SQ_OK;
 }
 
 }  // extern "C"

@@ -270,6 +270,63 @@ def test_batch_calls_reject_bad_tuning_chunk_and_workspace():
     assert lib.sq_batch_workspace(ct.byref(bad)) == 0
 
 
+def _key(lib, b):
+    n = lib.sq_batch_tuning_key(ct.byref(b), None, 0)
+    buf = ct.create_string_buffer(n + 1)
+    assert lib.sq_batch_tuning_key(ct.byref(b), buf, n + 1) == n
+    return buf.value.decode()
+
+
+def test_tuning_key_names_the_workload():
+    """The autotune cache key: one line without spaces that changes with every
+    scene shape, the grid, the march and the class count."""
+    lib = L.load()
+    b = _batch()
+    k = _key(lib, b)
+    assert k and " " not in k and "\n" not in k and k == _key(lib, _batch())
+    assert k.startswith("v%d|" % lib.sq_version())
+    short = ct.create_string_buffer(8)
+    assert lib.sq_batch_tuning_key(ct.byref(b), short, 8) == len(k) and short.value.decode() == k[:7]
+    assert lib.sq_batch_tuning_key(None, None, 0) == -1
+    for mutate in (lambda x: setattr(x.scenes[1], "width", 14), lambda x: setattr(x, "n_classes", 6),
+                   lambda x: setattr(x.march, "n_samples", 40), lambda x: setattr(x.grid, "voxel", 0.5),
+                   lambda x: setattr(x.scenes[2], "n_prims", 31)):
+        b2 = _batch()
+        mutate(b2)
+        assert _key(lib, b2) != k
+
+
+def test_autotune_cache_hit_launches_nothing(tmp_path):
+    """A cache line under the batch's key is returned without timing (nothing
+    is launched: on a host without a GPU any launch would fail); lines of other
+    keys, lines that do not parse and tunings the library cannot run are
+    skipped, the last matching line wins; the candidates are still validated."""
+    lib = L.load()
+    b, io = _batch(), _batch_io()
+    key = _key(lib, b)
+    path = tmp_path / "tuning.txt"
+    path.write_text("\n".join([
+        "some other workload => 4 2 0 1 4",
+        key + " => 16 2 1",                      # does not parse
+        key + " => 5 2 0 1 4",                   # tile width the library does not run
+        key + " => 8 2 0 1 4",
+        key + " => 16 4 0 1 8",                  # the last valid line wins
+    ]) + "\n")
+    cands = (L.SqTuning * 2)(L.SqTuning(8, 4, 0, 1, 4), L.SqTuning(16, 2, 0, 1, 4))
+    best, hit = L.SqTuning(), ct.c_int32(-1)
+    st = lib.sq_batch_autotune_cached(ct.byref(b), ct.byref(io), cands, 2, 1, str(path).encode(), ct.byref(best),
+                                      ct.byref(hit), 0x100000, 1 << 40, None)
+    assert st == L.SQ_OK, lib.sq_last_error()
+    assert hit.value == 1
+    assert (best.tile_w, best.waves_per_block, best.bwd_mode, best.persistent, best.chunk) == (16, 4, 0, 1, 8)
+    # an invalid candidate is rejected before the cache is read
+    bad = (L.SqTuning * 1)(L.SqTuning(5, 4, 0, 1, 4))
+    assert lib.sq_batch_autotune_cached(ct.byref(b), ct.byref(io), bad, 1, 1, str(path).encode(), ct.byref(best),
+                                        ct.byref(hit), 0x100000, 1 << 40, None) == L.SQ_ERR_INVALID
+    assert lib.sq_batch_autotune_cached(ct.byref(b), ct.byref(io), cands, 2, 1, str(path).encode(), None,
+                                        ct.byref(hit), 0x100000, 1 << 40, None) == L.SQ_ERR_INVALID
+
+
 @pytest.mark.parametrize("kappa", [-0.1, 1.5, float("nan"), float("inf")])
 def test_march_kappa_outside_unit_interval_is_rejected(kappa):
     lib = L.load()

@@ -133,6 +133,26 @@ def test_autotune_returns_a_timed_candidate():
     assert ms[cands.index(best)] == min(ms)
 
 
+def test_autotune_cache_round_trip(tmp_path):
+    """The cached autotuner times the candidates once and appends the winner
+    under the batch's key; the next call on the same workload reads it back
+    without timing, and another workload misses the cache."""
+    scenes = _small_batch(seed=91)
+    b = _make_batch(scenes)
+    cands = [api.Tuning(8, 4, 0, 0, 4), api.Tuning(16, 2, 0, 1, 8)]
+    path = tmp_path / "tuning.txt"
+    best, hit = b.autotune_cached(cands, path, reps=1)
+    assert not hit and best in cands
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith(b.tuning_key() + " => ")
+    again, hit = b.autotune_cached(cands, path, reps=1)
+    assert hit and again == best
+    other = _make_batch(_small_batch(seed=91, ns=(5, 0, 23, 12)))
+    assert other.tuning_key() != b.tuning_key()
+    third, hit = other.autotune_cached(cands, path, reps=1)
+    assert not hit and third in cands and len(path.read_text().splitlines()) == 2
+
+
 def test_batch_rejects_bad_tuning_without_launch():
     scenes = _small_batch(seed=95)
     b = _make_batch(scenes)
