@@ -489,7 +489,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 207; }
+int32_t sq_version(void) { return 208; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
