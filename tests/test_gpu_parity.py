@@ -178,7 +178,7 @@ def test_fwd_paper_render_setting_sampled_rays():
     _fwd_case(sc, ray_ids=ids, what="paper setting")
 
 
-@pytest.mark.parametrize("C", [5, 17])
+@pytest.mark.parametrize("C", [5, 17, 32])
 def test_fwd_bitmap_union_walk_equals_voxel_group_walk(C):
     """140k primitives: with one wave per block the per-wave union bitmap fits
     the LDS budget, with four it does not and mixed-voxel samples walk one
