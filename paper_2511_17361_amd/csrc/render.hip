@@ -123,7 +123,8 @@ __global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const 
     uint32_t glo, ghi;
     box_words(box, glo, ghi);
     r[R_GLO] = __uint_as_float(glo); r[R_GHI] = __uint_as_float(ghi);
-    r[R_AM1] = r[12] - 1.0f; r[R_BM1] = r[13] - 1.0f; r[R_EM1] = r[14] - 1.0f;
+    r[R_AM1] = r[12] == 1.0f ? FLT_MIN : r[12] - 1.0f;
+    r[R_BM1] = r[13] - 1.0f; r[R_EM1] = r[14] - 1.0f;
     r[22] = __int_as_float(box[0]); r[23] = __int_as_float(box[1]); r[24] = __int_as_float(box[2]);
     r[R_INVS] = is[0]; r[R_INVS + 1] = is[1]; r[R_INVS + 2] = is[2];
     for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < C ? logits[(size_t)k * C + c] : 0.0f;
@@ -783,34 +784,33 @@ __global__ __launch_bounds__(64 * VOX_WAVES) void k_voxelise(Ctx P) {
 // eq:sq_occupancy_prob with f of Sec. "SuperQuadrics"), added to an
 // accumulator row WITHOUT the primitive's constant factors; k_finalize
 // multiplies each row entry by its factor once per primitive (acc_factor).
-// With dfn = p dL/dp = -dL/df, base-2 logs and the split powers of eval_pair
-// (B/A = q_A, X/u = sign(u) q_u, ...):
+// With dfn = p dL/dp = -dL/df, base-2 logs and the ratios of eval_pair
+// (r_u = (B/A) X/|u|, r_v = (B/A) Y/|v|, q_w = Z/|w|):
 //   x[A_SIG]      += dL/da_j p                       (factor 1)
 //   x[A_E1]       += dfn (e B log2 A + b Z log2|w|)  (factor  ln2 b / 2)
-//   x[A_E2]       += dfn (B log2 A - a B/A S)        (factor -ln2 e a / 2)
-//                    S = X log2|u| + Y log2|v|
-//   g = dfn (B/A X/u, B/A Y/v, Z/w)                  (factors -e a/s_x,
+//   x[A_E2]       += dfn (B log2 A - a S)            (factor -ln2 e a / 2)
+//                    S = (B/A)(X log2|u| + Y log2|v|) = r_u |u| log2|u| + r_v |v| log2|v|
+//   g = dfn (sign(u) r_u, sign(v) r_v, sign(w) q_w)  (factors -e a/s_x,
 //   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c       -e a/s_y, -b/s_z)
-// Where |u|, |v|, |w| or A is 0 its log2 is -inf, but the power it multiplies
-// (X, Y, Z, B) is then exactly 0, and so is the limit of the product; those
-// products use the legacy multiply (0 x anything = 0), so no compare or select
-// is needed.  The same multiply keeps an infinite q_A (A = 0 with e < 1) out of
-// the sums: every factor it meets (X/u, Y/v, S) is 0 there.  With p = 0 every
-// term is exactly 0, so callers need not test p.
+// Where |u|, |v| or |w| is 0 its log2 is -inf, but the base it multiplies is
+// then exactly 0, and so is the limit of the product; those products use the
+// legacy multiply (0 x anything = 0), so no compare or select is needed.
+// Inside the cull box r_u, r_v, q_w, B and Z are finite; the products with
+// dfn still use the legacy multiply, so with p = 0 every term is exactly 0
+// and callers need not test p.
 // ---------------------------------------------------------------------------
 template <int VP, typename RecT>
 __device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, const float dd[3], float dfn,
                                              float da, float x[VP]) {
     const float a_ = r[12], b_ = r[13], e_ = r[14];
-    const float db = mul0(dfn, ev.qA);
-    const float g0 = mul0(with_sign_of(ev.qu, ev.u), db);
-    const float g1 = mul0(with_sign_of(ev.qv, ev.v), db);
+    const float g0 = mul0(dfn, with_sign_of(ev.ru, ev.u));
+    const float g1 = mul0(dfn, with_sign_of(ev.rv, ev.v));
     const float g2 = mul0(dfn, with_sign_of(ev.qw, ev.w));
-    const float bla = mul0(ev.B, ev.lA);
-    const float S = mul0(ev.X, ev.lu) + mul0(ev.Y, ev.lv);
+    const float bla = ev.B * ev.lA;
+    const float S = fmaf(ev.ru, mul0(fabsf(ev.u), ev.lu), ev.rv * mul0(fabsf(ev.v), ev.lv));
     x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
     x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * mul0(ev.Z, ev.lw)), x[A_E1]);
-    x[A_E2] = fmaf(dfn, fmaf(-a_, mul0(S, ev.qA), bla), x[A_E2]);
+    x[A_E2] = fmaf(dfn, fmaf(-a_, S, bla), x[A_E2]);
     x[A_XS + 0] += g0; x[A_XS + 1] += g1; x[A_XS + 2] += g2;
     x[A_R + 0] = fmaf(g0, dd[0], x[A_R + 0]);
     x[A_R + 1] = fmaf(g0, dd[1], x[A_R + 1]);

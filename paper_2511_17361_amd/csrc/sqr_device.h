@@ -8,6 +8,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <float.h>
 #include <stdint.h>
 
 namespace sqr {
@@ -21,8 +22,8 @@ namespace sqr {
 //   [16]     r_cull: max(|u|,|v|,|w|) >= r_cull  =>  f >= F_CULL
 //   [17..18] the clipped box of [22..24] in the packed-cell form of box_words
 //            (int bits; meaningful on grids within PV_MAX_XY x PV_MAX_XY x PV_MAX_Z)
-//   [19..21] a - 1, b - 1, e - 1 (the exponents of the split powers the
-//            adjoint evaluates, eval_pair)
+//   [19..21] a - 1 (FLT_MIN where it is 0), b - 1, e - 1 (the exponents
+//            of the ratios the adjoint evaluates, eval_pair)
 //   [22..24] clipped neighbourhood box per axis, int bits lo | hi << 16
 //            (the primitive is listed in voxel v iff v lies in this box)
 //   [25..27] 1/s
@@ -310,23 +311,36 @@ __device__ __forceinline__ float with_sign_of(float q, float x) {
     return __uint_as_float(__float_as_uint(q) | (__float_as_uint(x) & 0x80000000u));
 }
 
-// Evaluation for the adjoint.  Each power is split off its base, X = q_u |u|
-// with q_u = |u|^(a-1) = 2^((a-1) log2|u|), and likewise Y, Z and B = A^e =
-// q_A A, so the ratios the derivative chain needs come without reciprocals:
-// X/u = sign(u) q_u, Y/v = sign(v) q_v, Z/w = sign(w) q_w, B/A = q_A, and
-// p = 2^-((B + Z) log2 e).  p agrees with eval_p's to rounding (not bit for
-// bit).  At a base that is exactly 0 (a sample on a principal plane of the
-// primitive) the power's log is -inf: (k-1) log2 0 is 0 for k = 1 (legacy
-// multiply) and -inf for k > 1, so q_u, q_v and q_w stay finite for a, b >= 1
-// (eps1, eps2 <= 2, the paper's parameter range).  q_A is infinite at A = 0
-// when e < 1; pair_adjoint multiplies it only by factors that vanish there.
+// The sum A = |u|^a + |v|^a is formed in the log domain.  Its terms
+// underflow float32 long before the power B = A^e (e = eps2/eps1) becomes
+// negligible: at eps2 = 0.1 (a = 20) |u|^a is 0 below |u| = 0.006 while
+// A^e ~ max(|u|, |v|)^(2/eps1) is still of order |u| when eps1 is near 2, and
+// at the far end of the cull box |u|^a overflows where A^e is still finite.
+// With l_m = max(log2|u|, log2|v|) and d = min(log2|u|, log2|v|) - l_m <= 0,
+//   log2 A = a l_m + log2(1 + 2^(a d)),     log2 B = b l_m + e log2(1 + 2^(a d))
+// (b = a e), which stays finite and exact to rounding at any scale.  l_m is
+// floored at -LOG_FLOOR so that u = v = 0 (a sample on the primitive's third
+// axis) gives d = -inf and a finite, vanishing B instead of -inf - -inf.
+constexpr float LOG_FLOOR = 256.0f;
+
+// Evaluation for the adjoint.  Besides p it keeps the ratios the derivative
+// chain needs, each as one power of two with no reciprocal:
+//   r_u = (B/A) |u|^a / |u| = 2^((e-1) log2 A + (a-1) log2|u|),  r_v likewise,
+//   q_w = |w|^(b-1), Z = q_w |w|,
+// and p = 2^-((B + Z) log2 e).  p agrees with eval_p's to rounding (not bit
+// for bit).  At a base that is exactly 0 (a sample on a principal plane) its
+// log is -inf.  The record stores a - 1 as FLT_MIN where it is 0 (eps2 = 2),
+// so (a-1) log2|u| is -inf there too and r_u = 0, the symmetric subgradient
+// of |u| at its kink, with a plain FMA; q_w's (b-1) log2|w| is 0 for b = 1
+// (legacy multiply) and -inf for b > 1.  So r_u, r_v and q_w stay finite for
+// a, b >= 1 (eps1, eps2 <= 2, the paper's parameter range); log2 A is finite
+// by the floor above.  Inside the cull box every field is finite.
 // Returns false when the pair is culled (float32 exp(-f) would be exactly 0).
 struct PairEval {
     float u, v, w;         // canonical coordinates x_S / s
     float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
-    float qu, qv, qw;      // |u|^(a-1), |v|^(a-1), |w|^(b-1)
-    float X, Y, A, lA;     // |u|^a, |v|^a, A = X + Y, log2 A
-    float qA, B, Z;        // A^(e-1), A^e, |w|^b
+    float ru, rv, qw;      // (B/A) X/|u|, (B/A) Y/|v|, |w|^(b-1)
+    float lA, B, Z;        // log2 A, A^e, |w|^b
     float p;
 };
 
@@ -346,16 +360,15 @@ __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, flo
     e.lu = hw_log2(au);
     e.lv = hw_log2(av);
     e.lw = hw_log2(aw);
-    e.qu = hw_exp2(mul0(rec[R_AM1], e.lu));
-    e.qv = hw_exp2(mul0(rec[R_AM1], e.lv));
+    const float lm = fmaxf(fmaxf(e.lu, e.lv), -LOG_FLOOR);
+    const float d = fminf(e.lu, e.lv) - lm;
+    e.lA = fmaf(rec[12], lm, hw_log2(1.0f + hw_exp2(rec[12] * d)));
+    e.B = hw_exp2(rec[14] * e.lA);
+    const float c = rec[R_EM1] * e.lA;  // log2(B/A)
+    e.ru = hw_exp2(fmaf(rec[R_AM1], e.lu, c));
+    e.rv = hw_exp2(fmaf(rec[R_AM1], e.lv, c));
     e.qw = hw_exp2(mul0(rec[R_BM1], e.lw));
-    e.X = mul0(e.qu, au);
-    e.Y = mul0(e.qv, av);
     e.Z = mul0(e.qw, aw);
-    e.A = e.X + e.Y;
-    e.lA = hw_log2(e.A);
-    e.qA = hw_exp2(mul0(rec[R_EM1], e.lA));
-    e.B = mul0(e.qA, e.A);
     e.p = hw_exp2((e.B + e.Z) * -LOG2E);
     return true;
 }
@@ -370,9 +383,9 @@ __device__ __forceinline__ bool pair_kept(cf_ptr rec, float x, float y, float z)
 }
 
 // Evaluation of p alone (0 when culled): B and Z divided by ln 2 through the
-// exponent, so p = 2^-(Bs + Zs) takes no multiply.  The forward, the
-// backward's recompute and the voxelisation all call this, so they agree bit
-// for bit.
+// exponent, so p = 2^-(Bs + Zs) takes no multiply; B in the log form above.
+// The forward, the backward's recompute and the voxelisation all call this,
+// so they agree bit for bit.
 // eval_p_kept: false for a culled pair (p untouched), else p.
 template <typename RecT>
 __device__ __forceinline__ bool eval_p_kept(const RecT& rec, float x, float y, float z, float& p) {
@@ -384,10 +397,12 @@ __device__ __forceinline__ bool eval_p_kept(const RecT& rec, float x, float y, f
     const float mx = fmaxf(fmaxf(au, av), aw);
     if (!(mx < rec[16])) return false;
     const float a = rec[12], b = rec[13], ee = rec[14];
-    const float X = hw_exp2(a * hw_log2(au));
-    const float Y = hw_exp2(a * hw_log2(av));
+    const float lu = hw_log2(au), lv = hw_log2(av);
+    const float lm = fmaxf(fmaxf(lu, lv), -LOG_FLOOR);
+    const float d = fminf(lu, lv) - lm;
+    const float l1 = hw_log2(1.0f + hw_exp2(a * d));
     const float Zs = hw_exp2(fmaf(b, hw_log2(aw), L2_LOG2E));
-    const float Bs = hw_exp2(fmaf(ee, hw_log2(X + Y), L2_LOG2E));
+    const float Bs = hw_exp2(fmaf(ee, l1, fmaf(b, lm, L2_LOG2E)));
     p = hw_exp2(-(Bs + Zs));
     return true;
 }

@@ -248,6 +248,74 @@ def test_bwd_voxels_small_against_the_sample_spacing(voxel, dims, K):
     H.assert_grads_close(g, ref, f"small voxels {voxel} K{K}")
 
 
+@pytest.mark.parametrize("eps_pair", [(0.1, 0.1), (2.0, 2.0), (0.1, 2.0), (2.0, 0.1)])
+def test_fwd_bwd_at_the_ends_of_the_shape_range(eps_pair):
+    """Shape exponents at the ends of the paper's range [0.1, 2]: eps = 0.1
+    gives exponents 2/eps = 20 (near-box shapes, steep p), eps = 2 gives
+    exponent 1 (near-octahedra).  Forward and gradients against the oracle,
+    with half the primitives at each end pair and half random.  At (2, 0.1)
+    one primitive's samples pass within 1% of its third axis, where |u|^20
+    underflows float32 while (|u|^20 + |v|^20)^(1/20) is still about |u|."""
+    _say("fwd+bwd shape range ends", eps_pair)
+    sc = random_scene(48, n=24, n_classes=5, width=21, height=15, n_samples=33, opacity_hi=0.8,
+                      dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0)
+    sc.prims.eps[::2] = np.float32(eps_pair)
+    _fwd_case(sc, what=f"eps {eps_pair}")
+    rng = np.random.default_rng(48)
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, 5)
+    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=8, tuning=api.Tuning(8, 4, 2))
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    assert np.abs(ref["opacity"]).max() > 0, "the camera must see the primitives"
+    H.assert_grads_close(g, ref, f"eps {eps_pair}")
+
+
+def _quat_taking_to_z(d):
+    """(w, x, y, z) of the rotation that maps the unit vector d onto +z."""
+    q = np.array([1.0 + d[2], d[1], -d[0], 0.0])
+    return q / np.linalg.norm(q)
+
+
+def _rot(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+@pytest.mark.parametrize("eps1", [2.0, 1.5])
+def test_fwd_bwd_samples_near_the_third_axis_of_a_flat_exponent(eps1):
+    """Primitives with eps2 = 0.1 (a = 20) whose third local axis runs
+    parallel to a camera ray at 0.2% to 3% of s_x: along that ray |u| is the
+    offset and v is 0 to rounding, so |u|^a underflows float32 while
+    B = (|u|^a + |v|^a)^(eps2/eps1) is |u|^(2/eps1), of order |u|, and dB/du is
+    of order 1.  The kernels must form B in the log domain to match the
+    oracle here (forward values and every gradient)."""
+    _say("fwd+bwd near the third axis, eps1", eps1)
+    rays = synth.pinhole_rig(1, 21, 15, 90.0, (0.0, 0.0, 0.0))
+    picks = [(7, 10, 2.0, 0.002), (3, 4, 2.6, 0.005), (11, 16, 3.0, 0.01), (5, 13, 1.8, 0.03)]
+    scales = np.array([[0.8, 0.6, 1.0], [0.5, 0.7, 0.9], [1.0, 0.9, 0.6], [0.6, 0.6, 1.2]])
+    means, quats = [], []
+    for (row, col, t0, off), s in zip(picks, scales):
+        d = rays.dirs[0, row, col].astype(np.float64)
+        q = _quat_taking_to_z(d)
+        R = _rot(q)
+        assert np.allclose(R @ d, [0.0, 0.0, 1.0])
+        means.append(rays.origins[0, row, col] + t0 * d - off * s[0] * R[0])
+        quats.append(q)
+    rng = np.random.default_rng(7)
+    f32 = lambda a: np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32))
+    prims = synth.Prims(f32(means), f32(quats), f32(scales), f32([[eps1, 0.1]] * 4),
+                        f32([0.9, 0.7, 0.8, 0.6]), f32(rng.standard_normal((4, 3))))
+    sc = synth.Scene(synth.Grid(lo=(-4.0, -4.0, -2.0), voxel=0.5, dims=(16, 16, 8), nv=5), prims, rays,
+                     synth.March(48, 0.1, 5.0), name="near-axis")
+    _fwd_case(sc, what=f"near axis eps1 {eps1}")
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, 3)
+    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=8, tuning=api.Tuning(8, 4, 2))
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    assert np.abs(ref["means"]).min() > 0, "every primitive must be seen"
+    H.assert_grads_close(g, ref, f"near axis eps1 {eps1}")
+
+
 def test_bwd_forcing_primitive_major_where_it_does_not_apply_is_rejected():
     sc = random_scene(45, n=5, width=9, height=7)
     with pytest.raises(Exception, match="status -4"):
