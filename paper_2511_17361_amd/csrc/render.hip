@@ -124,7 +124,8 @@ __global__ __launch_bounds__(256) void k_prep_records(int n_total, int C, const 
     box_words(box, glo, ghi);
     r[R_GLO] = __uint_as_float(glo); r[R_GHI] = __uint_as_float(ghi);
     r[R_AM1] = r[12] == 1.0f ? FLT_MIN : r[12] - 1.0f;
-    r[R_BM1] = r[13] - 1.0f; r[R_EM1] = r[14] - 1.0f;
+    r[R_BM1] = r[13] == 1.0f ? FLT_MIN : r[13] - 1.0f;
+    r[R_EM1] = r[14] - 1.0f;
     r[22] = __int_as_float(box[0]); r[23] = __int_as_float(box[1]); r[24] = __int_as_float(box[2]);
     r[R_INVS] = is[0]; r[R_INVS + 1] = is[1]; r[R_INVS + 2] = is[2];
     for (int c = 0; c < CP; ++c) lgp[(size_t)k * CP + c] = c < C ? logits[(size_t)k * C + c] : 0.0f;
@@ -784,18 +785,18 @@ __global__ __launch_bounds__(64 * VOX_WAVES) void k_voxelise(Ctx P) {
 // eq:sq_occupancy_prob with f of Sec. "SuperQuadrics"), added to an
 // accumulator row WITHOUT the primitive's constant factors; k_finalize
 // multiplies each row entry by its factor once per primitive (acc_factor).
-// With dfn = p dL/dp = -dL/df, base-2 logs and the ratios of eval_pair
-// (r_u = (B/A) X/|u|, r_v = (B/A) Y/|v|, q_w = Z/|w|):
-//   x[A_SIG]      += dL/da_j p                       (factor 1)
-//   x[A_E1]       += dfn (e B log2 A + b Z log2|w|)  (factor  ln2 b / 2)
-//   x[A_E2]       += dfn (B log2 A - a S)            (factor -ln2 e a / 2)
-//                    S = (B/A)(X log2|u| + Y log2|v|) = r_u |u| log2|u| + r_v |v| log2|v|
-//   g = dfn (sign(u) r_u, sign(v) r_v, sign(w) q_w)  (factors -e a/s_x,
-//   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c       -e a/s_y, -b/s_z)
+// With dfn = p dL/dp = -dL/df, base-2 logs and the quantities of eval_pair,
+// which carry 1/ln 2 (B' = B/ln2, Z' = Z/ln2, r_u = (B/A) X/|u| / ln2, ...):
+//   x[A_SIG]      += dL/da_j p                         (factor 1)
+//   x[A_E1]       += dfn (e B' log2 A + b Z' log2|w|)  (factor  ln2^2 b / 2)
+//   x[A_E2]       += dfn (B' log2 A - a S)             (factor -ln2^2 e a / 2)
+//                    S = r_u |u| log2|u| + r_v |v| log2|v|
+//   g = dfn (sign(u) r_u, sign(v) r_v, sign(w) q_w)    (factors -ln2 e a/s_x,
+//   x[A_XS+i] += g_i, x[A_R+3i+c] += g_i (x-m)_c         -ln2 e a/s_y, -ln2 b/s_z)
 // Where |u|, |v| or |w| is 0 its log2 is -inf, but the base it multiplies is
 // then exactly 0, and so is the limit of the product; those products use the
 // legacy multiply (0 x anything = 0), so no compare or select is needed.
-// Inside the cull box r_u, r_v, q_w, B and Z are finite; the products with
+// Inside the cull box r_u, r_v, q_w, B' and Z' are finite; the products with
 // dfn still use the legacy multiply, so with p = 0 every term is exactly 0
 // and callers need not test p.
 // ---------------------------------------------------------------------------
@@ -827,14 +828,14 @@ __device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, 
 // pair_adjoint); 1 for the opacity and the logits.
 __device__ __forceinline__ float acc_factor(cf_ptr r, int vi) {
     const float a_ = r[12], b_ = r[13], e_ = r[14];
-    const float fu = -e_ * a_;
-    if (vi == A_E1) return 0.5f * LN2 * b_;
-    if (vi == A_E2) return -0.5f * LN2 * e_ * a_;
+    const float fu = -LN2 * e_ * a_, fw = -LN2 * b_;
+    if (vi == A_E1) return 0.5f * LN2 * LN2 * b_;
+    if (vi == A_E2) return -0.5f * LN2 * LN2 * e_ * a_;
     if (vi >= A_XS && vi < A_XS + 3)
-        return vi == A_XS + 2 ? -b_ * r[R_INVS + 2] : fu * r[R_INVS + vi - A_XS];
+        return vi == A_XS + 2 ? fw * r[R_INVS + 2] : fu * r[R_INVS + vi - A_XS];
     if (vi >= A_R && vi < A_R + 9) {
         const int i = (vi - A_R) / 3;
-        return i == 2 ? -b_ * r[R_INVS + 2] : fu * r[R_INVS + i];
+        return i == 2 ? fw * r[R_INVS + 2] : fu * r[R_INVS + i];
     }
     return 1.0f;
 }

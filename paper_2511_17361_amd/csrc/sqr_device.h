@@ -22,8 +22,8 @@ namespace sqr {
 //   [16]     r_cull: max(|u|,|v|,|w|) >= r_cull  =>  f >= F_CULL
 //   [17..18] the clipped box of [22..24] in the packed-cell form of box_words
 //            (int bits; meaningful on grids within PV_MAX_XY x PV_MAX_XY x PV_MAX_Z)
-//   [19..21] a - 1 (FLT_MIN where it is 0), b - 1, e - 1 (the exponents
-//            of the ratios the adjoint evaluates, eval_pair)
+//   [19..21] a - 1, b - 1 (each FLT_MIN where it is 0), e - 1 (the
+//            exponents of the ratios the adjoint evaluates, eval_pair)
 //   [22..24] clipped neighbourhood box per axis, int bits lo | hi << 16
 //            (the primitive is listed in voxel v iff v lies in this box)
 //   [25..27] 1/s
@@ -324,23 +324,25 @@ __device__ __forceinline__ float with_sign_of(float q, float x) {
 constexpr float LOG_FLOOR = 256.0f;
 
 // Evaluation for the adjoint.  Besides p it keeps the ratios the derivative
-// chain needs, each as one power of two with no reciprocal:
-//   r_u = (B/A) |u|^a / |u| = 2^((e-1) log2 A + (a-1) log2|u|),  r_v likewise,
-//   q_w = |w|^(b-1), Z = q_w |w|,
-// and p = 2^-((B + Z) log2 e).  p agrees with eval_p's to rounding (not bit
-// for bit).  At a base that is exactly 0 (a sample on a principal plane) its
-// log is -inf.  The record stores a - 1 as FLT_MIN where it is 0 (eps2 = 2),
-// so (a-1) log2|u| is -inf there too and r_u = 0, the symmetric subgradient
-// of |u| at its kink, with a plain FMA; q_w's (b-1) log2|w| is 0 for b = 1
-// (legacy multiply) and -inf for b > 1.  So r_u, r_v and q_w stay finite for
-// a, b >= 1 (eps1, eps2 <= 2, the paper's parameter range); log2 A is finite
-// by the floor above.  Inside the cull box every field is finite.
+// chain needs, each as one power of two with no reciprocal, and all of them
+// (with B and Z) divided by ln 2 through the exponent, like eval_p's:
+//   r_u = (B/A) |u|^a / |u| / ln2 = 2^((e-1) log2 A + (a-1) log2|u| + log2(1/ln2)),
+//   r_v likewise, q_w = |w|^(b-1) / ln2, Z = q_w |w|, B = A^e / ln2,
+// so p = 2^-(B + Z) takes no multiply; k_finalize puts ln 2 back into the
+// factors (acc_factor).  p agrees with eval_p's to rounding (not bit for
+// bit).  At a base that is exactly 0 (a sample on a principal plane) its log
+// is -inf.  The record stores a - 1 and b - 1 as FLT_MIN where they are 0
+// (eps = 2), so (a-1) log2|u| is -inf there too and r_u = 0, the symmetric
+// subgradient of |u| at its kink, with a plain FMA (likewise q_w).  So r_u,
+// r_v and q_w stay finite for a, b >= 1 (eps1, eps2 <= 2, the paper's
+// parameter range); log2 A is finite by the floor above.  Inside the cull box
+// every field is finite.
 // Returns false when the pair is culled (float32 exp(-f) would be exactly 0).
 struct PairEval {
     float u, v, w;         // canonical coordinates x_S / s
     float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
-    float ru, rv, qw;      // (B/A) X/|u|, (B/A) Y/|v|, |w|^(b-1)
-    float lA, B, Z;        // log2 A, A^e, |w|^b
+    float ru, rv, qw;      // (B/A) X/|u|, (B/A) Y/|v|, |w|^(b-1), each / ln 2
+    float lA, B, Z;        // log2 A, A^e / ln 2, |w|^b / ln 2
     float p;
 };
 
@@ -363,13 +365,13 @@ __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, flo
     const float lm = fmaxf(fmaxf(e.lu, e.lv), -LOG_FLOOR);
     const float d = fminf(e.lu, e.lv) - lm;
     e.lA = fmaf(rec[12], lm, hw_log2(1.0f + hw_exp2(rec[12] * d)));
-    e.B = hw_exp2(rec[14] * e.lA);
-    const float c = rec[R_EM1] * e.lA;  // log2(B/A)
+    e.B = hw_exp2(fmaf(rec[14], e.lA, L2_LOG2E));
+    const float c = fmaf(rec[R_EM1], e.lA, L2_LOG2E);  // log2(B/A / ln 2)
     e.ru = hw_exp2(fmaf(rec[R_AM1], e.lu, c));
     e.rv = hw_exp2(fmaf(rec[R_AM1], e.lv, c));
-    e.qw = hw_exp2(mul0(rec[R_BM1], e.lw));
-    e.Z = mul0(e.qw, aw);
-    e.p = hw_exp2((e.B + e.Z) * -LOG2E);
+    e.qw = hw_exp2(fmaf(rec[R_BM1], e.lw, L2_LOG2E));
+    e.Z = e.qw * aw;
+    e.p = hw_exp2(-(e.B + e.Z));
     return true;
 }
 
