@@ -316,6 +316,35 @@ def test_fwd_bwd_samples_near_the_third_axis_of_a_flat_exponent(eps1):
     H.assert_grads_close(g, ref, f"near axis eps1 {eps1}")
 
 
+@pytest.mark.parametrize("eps", [(2.0, 2.0), (1.0, 0.5), (2.0, 0.1), (0.5, 1.0)])
+def test_fwd_bwd_samples_exactly_on_principal_planes_and_axes(eps):
+    """The centre ray of an odd-sized image runs exactly along +x, and the
+    quaternions below give exact permutation matrices, so samples on that
+    ray have local coordinates that are exactly 0: v = w = 0 (identity),
+    u = v = 0 (the cyclic permutation taking x to the third axis) and w = 0
+    (identity, offset in y).  log2 0 = -inf then meets every exponent; at
+    eps = 2 (exponent 1) the derivative of |u| at 0 is taken as 0 on both
+    sides.  Forward values and every gradient against the oracle."""
+    _say("fwd+bwd exact zeros, eps", eps)
+    rays = synth.pinhole_rig(1, 21, 15, 90.0, (0.0, 0.0, 0.0))
+    assert (rays.dirs[0, 7, 10] == np.float32([1.0, 0.0, 0.0])).all()
+    ident, cyc = [1.0, 0.0, 0.0, 0.0], [0.5, -0.5, -0.5, -0.5]
+    f32 = lambda a: np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32))
+    rng = np.random.default_rng(11)
+    prims = synth.Prims(f32([[2.0, 0.0, 0.0], [3.0, 0.0, 0.0], [1.5, 0.2, 0.0], [2.5, 0.0, 0.0]]),
+                        f32([ident, cyc, ident, cyc]),
+                        f32([[0.4, 0.3, 0.5], [0.5, 0.4, 0.3], [0.3, 0.6, 0.4], [0.35, 0.35, 0.45]]),
+                        f32([eps] * 4), f32([0.8, 0.9, 0.6, 0.7]), f32(rng.standard_normal((4, 3))))
+    sc = synth.Scene(synth.Grid(lo=(-4.0, -4.0, -2.0), voxel=0.5, dims=(16, 16, 8), nv=5), prims, rays,
+                     synth.March(48, 0.1, 5.0), name="exact-zeros")
+    _fwd_case(sc, what=f"exact zeros eps {eps}")
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, 3)
+    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=8, tuning=api.Tuning(8, 4, 2))
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    assert np.abs(ref["opacity"]).min() > 0, "every primitive must be seen"
+    H.assert_grads_close(g, ref, f"exact zeros eps {eps}")
+
+
 def test_bwd_forcing_primitive_major_where_it_does_not_apply_is_rejected():
     sc = random_scene(45, n=5, width=9, height=7)
     with pytest.raises(Exception, match="status -4"):
