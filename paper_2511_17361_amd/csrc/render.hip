@@ -808,7 +808,7 @@ __device__ __forceinline__ void pair_adjoint(const RecT& r, const PairEval& ev, 
     const float g1 = mul0(dfn, with_sign_of(ev.rv, ev.v));
     const float g2 = mul0(dfn, with_sign_of(ev.qw, ev.w));
     const float bla = ev.B * ev.lA;
-    const float S = fmaf(ev.ru, mul0(fabsf(ev.u), ev.lu), ev.rv * mul0(fabsf(ev.v), ev.lv));
+    const float S = mul0(ev.Xb, ev.lu) + mul0(ev.Yb, ev.lv);
     x[A_SIG] = fmaf(da, ev.p, x[A_SIG]);
     x[A_E1] = fmaf(dfn, fmaf(e_, bla, b_ * mul0(ev.Z, ev.lw)), x[A_E1]);
     x[A_E2] = fmaf(dfn, fmaf(-a_, S, bla), x[A_E2]);

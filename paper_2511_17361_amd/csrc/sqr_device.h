@@ -327,8 +327,9 @@ constexpr float LOG_FLOOR = 256.0f;
 // chain needs, each as one power of two with no reciprocal, and all of them
 // (with B and Z) divided by ln 2 through the exponent, like eval_p's:
 //   r_u = (B/A) |u|^a / |u| / ln2 = 2^((e-1) log2 A + (a-1) log2|u| + log2(1/ln2)),
-//   r_v likewise, q_w = |w|^(b-1) / ln2, Z = q_w |w|, B = A^e / ln2,
-// so p = 2^-(B + Z) takes no multiply; k_finalize puts ln 2 back into the
+//   r_v likewise, q_w = |w|^(b-1) / ln2, Z = q_w |w|, and B = A^e / ln2 as
+// r_u |u| + r_v |v| = (B/A)(X + Y) / ln2 (no power of its own), so
+// p = 2^-(B + Z) takes no multiply; k_finalize puts ln 2 back into the
 // factors (acc_factor).  p agrees with eval_p's to rounding (not bit for
 // bit).  At a base that is exactly 0 (a sample on a principal plane) its log
 // is -inf.  The record stores a - 1 and b - 1 as FLT_MIN where they are 0
@@ -342,7 +343,8 @@ struct PairEval {
     float u, v, w;         // canonical coordinates x_S / s
     float lu, lv, lw;      // log2 |u|, log2 |v|, log2 |w|
     float ru, rv, qw;      // (B/A) X/|u|, (B/A) Y/|v|, |w|^(b-1), each / ln 2
-    float lA, B, Z;        // log2 A, A^e / ln 2, |w|^b / ln 2
+    float Xb, Yb;          // r_u |u| = (B/A) X / ln 2, r_v |v| = (B/A) Y / ln 2
+    float lA, B, Z;        // log2 A, A^e / ln 2 = Xb + Yb, |w|^b / ln 2
     float p;
 };
 
@@ -365,10 +367,12 @@ __device__ __forceinline__ bool eval_pair(const RecT& rec, float x, float y, flo
     const float lm = fmaxf(fmaxf(e.lu, e.lv), -LOG_FLOOR);
     const float d = fminf(e.lu, e.lv) - lm;
     e.lA = fmaf(rec[12], lm, hw_log2(1.0f + hw_exp2(rec[12] * d)));
-    e.B = hw_exp2(fmaf(rec[14], e.lA, L2_LOG2E));
     const float c = fmaf(rec[R_EM1], e.lA, L2_LOG2E);  // log2(B/A / ln 2)
     e.ru = hw_exp2(fmaf(rec[R_AM1], e.lu, c));
     e.rv = hw_exp2(fmaf(rec[R_AM1], e.lv, c));
+    e.Xb = e.ru * au;
+    e.Yb = e.rv * av;
+    e.B = e.Xb + e.Yb;
     e.qw = hw_exp2(fmaf(rec[R_BM1], e.lw, L2_LOG2E));
     e.Z = e.qw * aw;
     e.p = hw_exp2(-(e.B + e.Z));
