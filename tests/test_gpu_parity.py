@@ -269,6 +269,25 @@ def test_fwd_bwd_at_the_ends_of_the_shape_range(eps_pair):
     H.assert_grads_close(g, ref, f"eps {eps_pair}")
 
 
+@pytest.mark.parametrize("seed", [61, 62, 63, 64, 65, 66])
+def test_fwd_bwd_random_shapes_over_the_whole_eps_range(seed):
+    """Random scenes whose eps1, eps2 are uniform over the paper's whole range
+    [0.1, 2] (the synthetic workloads draw from [0.2, 1.8]), 40 primitives
+    of scales 0.2..1.5 in front of one camera.  Forward and gradients
+    against the oracle."""
+    _say("fwd+bwd random eps over [0.1, 2], seed", seed)
+    sc = random_scene(seed, n=40, n_classes=4, width=19, height=13, n_samples=40, opacity_hi=0.9,
+                      dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0, scale_lo=0.2, scale_hi=1.5)
+    rng = np.random.default_rng(seed)
+    sc.prims.eps[:] = rng.uniform(0.1, 2.0, sc.prims.eps.shape).astype(np.float32)
+    _fwd_case(sc, what=f"random eps seed {seed}")
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, 4)
+    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=8, tuning=api.Tuning(8, 4, 2))
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    assert np.abs(ref["opacity"]).max() > 0, "the camera must see the primitives"
+    H.assert_grads_close(g, ref, f"random eps seed {seed}")
+
+
 def _quat_taking_to_z(d):
     """(w, x, y, z) of the rotation that maps the unit vector d onto +z."""
     q = np.array([1.0 + d[2], d[1], -d[0], 0.0])
