@@ -288,6 +288,30 @@ def test_fwd_bwd_random_shapes_over_the_whole_eps_range(seed):
     H.assert_grads_close(g, ref, f"random eps seed {seed}")
 
 
+@pytest.mark.parametrize("seed", [71, 72])
+def test_fwd_bwd_scale_and_quaternion_norm_extremes(seed):
+    """Primitives thinner than the sample spacing (s = 0.03..0.08 against a
+    spacing of 0.17), primitives spanning most of the grid (s = 2.5..4),
+    and quaternions of norm 0.01 and 30 (the renderer uses r/|r|, so the
+    quaternion gradient is tangent to the sphere and scales with 1/|r|).
+    Forward and gradients against the oracle."""
+    _say("fwd+bwd scale / quaternion-norm extremes, seed", seed)
+    sc = random_scene(seed, n=24, n_classes=3, width=17, height=13, n_samples=40, opacity_hi=0.9,
+                      dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0)
+    rng = np.random.default_rng(seed)
+    sc.prims.scales[0:6] = rng.uniform(0.03, 0.08, (6, 3)).astype(np.float32)
+    sc.prims.scales[6:10] = rng.uniform(2.5, 4.0, (4, 3)).astype(np.float32)
+    sc.prims.quats[10:16] *= np.float32(0.01)
+    sc.prims.quats[16:20] *= np.float32(30.0)
+    _fwd_case(sc, what=f"extremes seed {seed}")
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, 3)
+    _, g = H.run_fwd_bwd(sc, g_d, g_s, ckpt_every=8, tuning=api.Tuning(8, 4, 2))
+    ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    assert np.abs(ref["opacity"][0:6]).max() > 0 and np.abs(ref["opacity"][6:10]).max() > 0, \
+        "thin and large primitives must be seen"
+    H.assert_grads_close(g, ref, f"extremes seed {seed}")
+
+
 def _quat_taking_to_z(d):
     """(w, x, y, z) of the rotation that maps the unit vector d onto +z."""
     q = np.array([1.0 + d[2], d[1], -d[0], 0.0])
