@@ -384,6 +384,30 @@ typedef struct {
      * with chunk K needs ceil(L/K) * (sum of rays) of them; fewer:
      * SQ_ERR_CAPACITY, nothing launched. */
     int64_t  ckpt_len;
+    /* Per-sample values of the last forward (nullable; an MI355X-side design
+     * choice, not in the paper: it trades HBM for the backward's recompute).
+     * A forward with checkpoints gives every chunk of K samples that a ray
+     * tile enters one slot of the buffer's pool, in the order the tiles reach
+     * their chunks, and leaves there, for each sample it composites, the
+     * density sum a_j = sum_k p sigma_k and the class sums s_j = sum_k p c_k
+     * of Eq. eq:alpha_sem_sq.  The primitive-major backward then takes a_j
+     * and G_j = <g_S, s_j> from the slot instead of evaluating the chunk's
+     * pairs a first time; a chunk without a slot (pool exhausted) is
+     * recomputed as without the buffer.  Layout (int32 words at the start):
+     * [0] tile width, [1] L, [2] K, [3] 1 when a forward with checkpoints
+     * wrote it (a forward without checkpoints writes 0), [4] the slots that
+     * forward asked for (one per chunk entered, also beyond the pool: the
+     * figure to size the pool by), [5] the slots the pool holds; then the
+     * slot table and the pool (sizes from sq_batch_stash_len).  The backward
+     * uses it only when the header matches its own tiling, L and K; like the
+     * checkpoints it belongs to the last forward: pass it to both calls or to
+     * neither.  The counting variants (stats) ignore it. */
+    float*   stash;
+    /* Floats that io->stash holds: at least sq_batch_stash_len(batch,
+     * tuning, 0) for a call with checkpoints (16 for one without); fewer:
+     * SQ_ERR_CAPACITY, nothing launched.  Floats beyond that give
+     * (stash_len - sq_batch_stash_len(.., 0)) / slot size slots. */
+    int64_t  stash_len;
 } sq_batch_io;
 
 /* Bytes of workspace every batched call needs (host-only; 0 on bad input). */
@@ -392,6 +416,14 @@ size_t sq_batch_workspace(const sq_batch* batch);
 /* Length (int32) of io->tile_stop for calls with this tuning (its tile width;
  * NULL = defaults).  Host-only; 0 on bad input. */
 int64_t sq_batch_tile_stop_len(const sq_batch* batch, const sq_tuning* tuning);
+
+/* Floats of io->stash for calls with this tuning (its tile width and chunk;
+ * NULL = defaults) whose pool holds `slots` slots of one (tile, chunk) each:
+ * the header and slot table, 256-byte aligned, then slots x K x 64 x (Q + 2)
+ * floats, Q = the class count padded to 4, 8, 16 or 32 (16 at 17 classes).
+ * Host-only; 0 on bad input (a chunk outside {4, 8, 16}, slots < 0 or above
+ * INT32_MAX). */
+int64_t sq_batch_stash_len(const sq_batch* batch, const sq_tuning* tuning, int64_t slots);
 
 /* sq_build_index for every scene of the batch (Sec. 3.3 "Preliminary
  * Construction").  Writes counts, offsets, ids (below each scene's capacity)

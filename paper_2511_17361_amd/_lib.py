@@ -28,8 +28,10 @@ EXPORTED = [
     "sq_voxelise_workspace", "sq_voxelise", "sq_batch_voxelise",
     "sq_render_fwd_loss", "sq_batch_render_fwd_loss", "sq_batch_train_step", "sq_batch_train_graph_create",
     "sq_sq_major_workspace", "sq_render_bwd_sq_major", "sq_batch_tile_stop_len", "sq_render_fwd_noalloc",
-    "sq_batch_autotune_cached", "sq_batch_tuning_key",
+    "sq_batch_autotune_cached", "sq_batch_tuning_key", "sq_batch_stash_len",
 ]
+# int32 words of the stash header: tile width, L, K, written, slots asked for, slots held
+SQ_STASH_HEAD = 16
 SQ_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
@@ -92,7 +94,7 @@ class SqBatchIO(ct.Structure):
         "counts", "offsets", "ids", "totals", "depth", "sem", "probs", "t_final", "ckpt",
         "g_depth", "g_sem", "g_means", "g_quats", "g_scales", "g_eps", "g_opacity", "g_logits",
         "vox_density", "vox_sem", "vox_labels", "sem_label", "depth_label", "loss", "tile_stop")] + [
-        ("tile_stop_len", ct.c_int64), ("ckpt_len", ct.c_int64)]
+        ("tile_stop_len", ct.c_int64), ("ckpt_len", ct.c_int64), ("stash", ct.c_void_p), ("stash_len", ct.c_int64)]
 
 
 class SqLossWeights(ct.Structure):
@@ -139,6 +141,8 @@ def load(path: str = LIB_PATH) -> ct.CDLL:
     lib.sq_batch_workspace.argtypes = [P(SqBatch)]
     lib.sq_batch_tile_stop_len.restype = ct.c_int64
     lib.sq_batch_tile_stop_len.argtypes = [P(SqBatch), P(SqTuning)]
+    lib.sq_batch_stash_len.restype = ct.c_int64
+    lib.sq_batch_stash_len.argtypes = [P(SqBatch), P(SqTuning), ct.c_int64]
     lib.sq_batch_build_index.restype = ct.c_int32
     lib.sq_batch_build_index.argtypes = [P(SqBatch), P(SqBatchIO), ct.c_void_p, ct.c_size_t, ct.c_void_p]
     for fn in (lib.sq_batch_render_fwd, lib.sq_batch_render_bwd):

@@ -368,7 +368,7 @@ def render_bwd_stats(grid, index: Index, prims: Prims, rays: Rays, march, ckpt, 
 _IO_FIELDS = ("means", "quats", "scales", "eps", "opacity", "logits", "origins", "dirs", "counts", "offsets", "ids",
               "totals", "depth", "sem", "probs", "t_final", "ckpt", "g_depth", "g_sem", "g_means", "g_quats",
               "g_scales", "g_eps", "g_opacity", "g_logits", "vox_density", "vox_sem", "vox_labels", "sem_label",
-              "depth_label", "loss", "tile_stop")
+              "depth_label", "loss", "tile_stop", "stash")
 
 # Loss weights of the paper (Supplement "Loss Formulation"): lambda_s = 2, lambda_d = 0.05.
 PAPER_LOSS = (2.0, 0.05)
@@ -524,7 +524,33 @@ class Batch:
             io.tile_stop_len = int(vals["tile_stop"].numel())
         if vals.get("ckpt") is not None:
             io.ckpt_len = int(vals["ckpt"].numel())
+        if vals.get("stash") is not None:
+            io.stash_len = int(vals["stash"].numel())
         return io
+
+    def set_stash(self, slots: Optional[int], tuning: Optional[Tuning] = None):
+        """Give the batch a per-sample stash (sq_batch_io.stash) whose pool
+        holds `slots` slots for `tuning` (its tile width and chunk), or, with
+        no tuning, at least `slots` for every tile width and primitive-major
+        chunk (4 or 8); 0 keeps only the header and slot table, which still
+        count the slots a forward asks for (stash_demand); None removes it.  A
+        captured graph keeps the buffer it was captured with: capture again."""
+        self.release_graph()
+        if slots is None:
+            self.buf.pop("stash", None)
+            return
+        lib = L.load()
+        tunings = [tuning] if tuning is not None else [Tuning(tile_w=tw, chunk=k) for tw in (4, 8, 16) for k in (4, 8)]
+        n = max(int(lib.sq_batch_stash_len(ct.byref(self.c_batch), ct.byref(t.c()), int(slots))) for t in tunings)
+        if n <= 0:
+            raise ValueError(f"no stash layout for {slots} slots")
+        self.buf["stash"] = torch.zeros(n, dtype=torch.float32, device=self.device)
+
+    def stash_demand(self) -> int:
+        """Slots the last forward with checkpoints asked for (one per chunk a
+        ray tile entered); reads the device, so it synchronises."""
+        st = self.buf.get("stash")
+        return 0 if st is None else int(st[:L.SQ_STASH_HEAD].view(torch.int32)[4].item())
 
     def _call(self, fn, *args):
         L.check(fn(ct.byref(self.c_batch), ct.byref(self.io()), *args))

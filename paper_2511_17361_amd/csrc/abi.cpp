@@ -271,6 +271,7 @@ sqr::BatchIO to_dev(const sq_batch_io* io) {
     b.vox_density = io->vox_density; b.vox_sem = io->vox_sem; b.vox_labels = io->vox_labels;
     b.sem_label = io->sem_label; b.depth_label = io->depth_label; b.loss = io->loss;
     b.tile_stop = io->tile_stop;
+    b.stash = io->stash; b.stash_len = io->stash_len;
     return b;
 }
 
@@ -292,6 +293,17 @@ sq_status check_tile_stop(const Plan& p, const sq_batch_io* io) {
     if (io->tile_stop_len < need)
         return fail(SQ_ERR_CAPACITY, "tile_stop_len %lld < %lld for this tiling", (long long)io->tile_stop_len,
                     (long long)need);
+    return SQ_OK;
+}
+
+// The per-sample stash (nullable): at least its header, and for a call that
+// reads or writes it with chunk K (> 0) its slot table for this tiling.
+sq_status check_stash(const Plan& p, const sq_batch_io* io, int K) {
+    if (!io->stash) return SQ_OK;
+    const int64_t need = K > 0 ? sqr::stash_geom(p.d, p.m.n_samples, K).pool_off : sqr::STASH_HEAD;
+    if (io->stash_len < need)
+        return fail(SQ_ERR_CAPACITY, "stash_len %lld < %lld floats (header and slot table) for this tiling",
+                    (long long)io->stash_len, (long long)need);
     return SQ_OK;
 }
 
@@ -318,6 +330,7 @@ sq_status fwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
     const int K = chunk_of(tuning, p.m);
     if ((s = check_ckpt(p, io, K))) return s;
     if ((s = check_tile_stop(p, io))) return s;
+    if ((s = check_stash(p, io, io->ckpt ? K : 0))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
     if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
@@ -339,6 +352,7 @@ sq_status bwd_checked(const Plan& p, const sq_batch_io* io, int64_t* stats, cons
                                 !io->g_logits))
         return fail(SQ_ERR_INVALID, "a gradient output array is NULL");
     if ((s = check_tile_stop(p, io))) return s;
+    if ((s = check_stash(p, io, K))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
     if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
@@ -372,6 +386,7 @@ sq_status fwd_loss_checked(const Plan& p, const sq_batch_io* io, const sq_loss_w
     const int K = chunk_of(tuning, p.m);
     if ((s = check_ckpt(p, io, K))) return s;
     if ((s = check_tile_stop(p, io))) return s;
+    if ((s = check_stash(p, io, io->ckpt ? K : 0))) return s;
     sqr::TuneDev tune;
     if ((s = tuning_of(tuning, tune))) return s;
     if ((s = check_ws(ws, ws_bytes, sqr::batch_workspace_bytes(p.g, p.d)))) return s;
@@ -465,6 +480,7 @@ sq_status check_candidates(const sq_batch* b, const sq_batch_io* io, const sq_tu
         if (!io->ckpt) return fail(SQ_ERR_INVALID, "autotune times full steps: ckpt is NULL");
         if ((s = check_ckpt(p, io, K))) return s;
         if ((s = check_tile_stop(p, io))) return s;
+        if ((s = check_stash(p, io, K))) return s;
         if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
             !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
             return fail(SQ_ERR_UNSUPPORTED, "candidate %d: primitive-major backward does not apply", i);
@@ -489,7 +505,7 @@ extern "C" {
 
 const char* sq_last_error(void) { return g_err; }
 
-int32_t sq_version(void) { return 208; }
+int32_t sq_version(void) { return 209; }
 
 sq_tuning sq_default_tuning(void) { return default_tuning(); }
 
@@ -707,6 +723,18 @@ int64_t sq_batch_tile_stop_len(const sq_batch* b, const sq_tuning* tuning) {
     return 4 + (int64_t)p.d.total_tiles;
 }
 
+int64_t sq_batch_stash_len(const sq_batch* b, const sq_tuning* tuning, int64_t slots) {
+    sqr::TuneDev tune;
+    if (slots < 0 || tuning_of(tuning, tune)) return 0;
+    Plan p;
+    if (make_plan(b, tune.tile_w, p)) return 0;
+    const int K = chunk_of(tuning, p.m);
+    if (!chunk_ok(K)) return 0;
+    const sqr::StashGeom g = sqr::stash_geom(p.d, p.m.n_samples, K);
+    if (slots > (int64_t)INT32_MAX || slots > (INT64_MAX - g.pool_off) / g.slot_floats) return 0;
+    return g.pool_off + slots * g.slot_floats;
+}
+
 size_t sq_batch_workspace(const sq_batch* b) {
     Plan p;
     if (make_plan(b, 4, p)) return 0;
@@ -785,6 +813,7 @@ sq_status check_step(const sq_batch* b, const sq_batch_io* io, const sq_tuning* 
     if (!chunk_ok(K)) return fail(SQ_ERR_INVALID, "step needs a chunk in {4, 8, 16}");
     if ((s = check_ckpt(p, io, K))) return s;
     if ((s = check_tile_stop(p, io))) return s;
+    if ((s = check_stash(p, io, K))) return s;
     if (tune.bwd_mode == SQ_BWD_PRIMITIVE_MAJOR &&
         !sqr::bwd_primitive_major_ok(p.g, p.d.max_n, K, tune.waves_per_block))
         return fail(SQ_ERR_UNSUPPORTED, "primitive-major backward does not apply");

@@ -46,6 +46,17 @@ int padded_classes(int C) {
 }
 int acc_row(int CP) { return A_LG + CP <= 32 ? 32 : 64; }
 
+StashGeom stash_geom(const BatchDesc& d, int L, int K) {
+    StashGeom g;
+    const int CP = padded_classes(d.C);
+    g.m_floats = CP >= 16 ? CP / 16 * 16 : CP >= 8 ? 8 : 4;
+    g.nck = K > 0 ? (L + K - 1) / K : 0;
+    g.tab_off = STASH_HEAD;
+    g.pool_off = (STASH_HEAD + (int64_t)d.total_tiles * g.nck + 63) / 64 * 64;
+    g.slot_floats = (int64_t)K * 64 * (g.m_floats + 2);
+    return g;
+}
+
 // Occupancy targets (waves per SIMD) that the register allocator must meet.
 // At 6 the persistent forward with checkpoints spills a few per-tile pointers
 // (stored at the tile's start, reloaded for its epilogue), which costs less
@@ -84,6 +95,12 @@ struct Ctx {
     // checkpoints wrote it, then per global tile the last sample its forward
     // composited
     int* tile_stop;
+    // nullable: the per-sample stash (StashGeom): header, slot table, pool
+    int* stash_hdr;
+    int* stash_tab;
+    float* stash_pool;
+    int stash_slots;            // slots the pool holds
+    int stash_slot_floats;
 };
 constexpr int STOP_HEAD = 4;
 
@@ -141,6 +158,15 @@ __global__ __launch_bounds__(256) void k_fill(float* __restrict__ p, int64_t n, 
 __global__ __launch_bounds__(64) void k_stop_header(int* __restrict__ tab, int tile_w, int L, int K, int written) {
     if (threadIdx.x == 0) {
         tab[0] = tile_w; tab[1] = L; tab[2] = K; tab[3] = written;
+    }
+}
+
+// Header of the stash before a forward: its tiling, march and slot count, the
+// request counter cleared, and whether the forward writes the stash.
+__global__ __launch_bounds__(64) void k_stash_header(int* __restrict__ h, int tile_w, int L, int K, int written,
+                                                     int slots) {
+    if (threadIdx.x == 0) {
+        h[0] = tile_w; h[1] = L; h[2] = K; h[3] = written; h[4] = 0; h[5] = slots;
     }
 }
 
@@ -404,6 +430,11 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
 
     using CS = ClassSums<CP>;
     const LogitRows<CP> LR(X.lgp, X.n, lane);
+    static_assert(CS::NX <= 1, "the stash holds at most one class beyond the four-wide accumulators");
+    // the stash (forward with checkpoints): each chunk the tile enters takes a
+    // slot of the pool, where the chunk's samples leave a and their class sums
+    int* const stab = (CKPT && P.stash_tab) ? P.stash_tab + (int64_t)(S.tile_off + tile) * nck : nullptr;
+    int stash_slot = -1;
 
     float T = rl.valid ? 1.0f : 0.0f;
     float D = 0.0f;
@@ -426,6 +457,17 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
             if (alive && nxt.v >= 0) { n_nxt = X.counts[nxt.v]; f_nxt = X.offsets[nxt.v]; }
         }
         if (CKPT && (j % K) == 0 && rl.valid) ckpt[(int64_t)(j / K) * R] = T;
+        if (CKPT && stab && (j % K) == 0) {
+            // one request per chunk, by the wave's first active lane
+            const int lead = __builtin_ctzll(wave_ballot(true));
+            int sl = 0;
+            if (lane == lead) {
+                sl = atomicAdd(P.stash_hdr + 4, 1);
+                stab[j / K] = sl < P.stash_slots ? sl : -1;
+            }
+            sl = readlane_i(sl, lead);
+            stash_slot = sl < P.stash_slots ? sl : -1;
+        }
         // a ray that has left the grid for good adds nothing more; once every
         // lane has, the tile stops as it does when all rays are opaque
         if ((j & 3) == 0) alive = alive && !left_grid(P.g, cur, rl.dx, rl.dy, rl.dz);
@@ -519,6 +561,17 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                     pend = pend && !mine;
                 }
             }
+            if (CKPT && stash_slot >= 0 && act) {
+                float* const sp = P.stash_pool + (int64_t)stash_slot * P.stash_slot_floats;
+                const int jl = (j % K) * 64 + lane;
+                f32x4_t* const mp = reinterpret_cast<f32x4_t*>(sp + (int64_t)jl * (4 * CS::NM));
+#pragma unroll
+                for (int i = 0; i < CS::NM; ++i) mp[i] = sv.m[i];
+                float2 e;
+                e.x = CS::NX > 0 ? sv.x[0] : 0.0f;
+                e.y = a;
+                reinterpret_cast<float2*>(sp + (int64_t)K * 64 * (4 * CS::NM))[jl] = e;
+            }
             // Eq. eq:alpha_composite and eq:depth_sem
             const float alpha = fminf(a, 1.0f);
             const float w = T * alpha;
@@ -531,6 +584,9 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
             // every later sample of this tile is exactly zero
             if (CKPT && rl.valid)
                 for (int c = j / K + 1; c * K < L; ++c) ckpt[(int64_t)c * R] = T;
+            // the chunks the tile does not enter have no slot
+            if (CKPT && stab && lane == __builtin_ctzll(wave_ballot(true)))
+                for (int c = j / K + 1; c < nck; ++c) stab[c] = -1;
             j_stop = j;
             break;
         }
@@ -1099,6 +1155,15 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
             stop = v < -1 ? -1 : v > L - 1 ? L - 1 : v;
         }
     }
+    // the forward's per-sample values (stash), when that forward wrote them
+    // with this tiling and chunk; the counting variant always recomputes
+    const int* stab = nullptr;
+    if (!STATS && P.stash_tab) {
+        const int* h = P.stash_hdr;
+        if (h[3] == 1 && h[0] == P.desc->tile_w && h[1] == L && h[2] == KC)
+            stab = P.stash_tab + (int64_t)(S.tile_off + tile) * nck;
+    }
+    using CS = ClassSums<CP>;
     float Q = 0.0f;
     for (int ci = nck - 1; ci >= 0; --ci) {
         if (ci * KC > stop) continue;
@@ -1152,45 +1217,85 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
         }
         wave_lds_sync();
 
-        // ---- pass 1: a_j and G_j over the union, ascending id ---------------
+        // ---- a_j and G_j: from the forward's stash, else pass 1 --------------
         float a[KC], G[KC];
 #pragma unroll
         for (int jj = 0; jj < KC; ++jj) { a[jj] = 0.0f; G[jj] = 0.0f; }
-        for_each_marked(bm, nw, lane, [&](int k) {
-            const cf_ptr r = X.rec_at(k);
-            Pinned<19> rr;
-            Pinned<CP> lg;
-            pin2(r, rr, X.template lgp_at<CP>(k), lg);
-            bool mem[KC];
-            pv.members(__float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_GHI]), mem);
-            bool anym = false;
-#pragma unroll
-            for (int jj = 0; jj < KC; ++jj) anym |= mem[jj];
-            if (wave_ballot(anym) == 0) return;
-            const float sig = rr[15];
-            // gamma up front: the sums are then updated inside each sample's
-            // branch, and a culled pair costs no default value of p
-            const float gam = gamma_of(lg);
-            bool hit = false;
+        const int slot = stab ? stab[ci] : -1;
+        if (slot >= 0 && slot < P.stash_slots) {
+            // a_j as the forward summed it and G_j = <g_S, s_j> from its class
+            // sums s_j = sum_k p c_k; samples the forward did not composite hold
+            // stale values, which the compositing below never reads
+            // through a buffer resource on the slot: the lane's offset in a
+            // register, each sample's offset a scalar constant
+            const float* const sp = P.stash_pool + (int64_t)slot * P.stash_slot_floats;
+            const __amdgpu_buffer_rsrc_t srs =
+                __builtin_amdgcn_make_buffer_rsrc((void*)sp, 0, (int)(KC * 64 * (4 * CS::NM + 2) * sizeof(float)),
+                                                  0x00020000);
+            constexpr int MB = 4 * CS::NM * (int)sizeof(float);     // class-sum bytes per lane and sample
+            const uint32_t vm = (uint32_t)lane * MB, ve = (uint32_t)lane * 8u;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
-                if (mem[jj]) {
-                    if (STATS) { st[1] += 1; if (pair_kept(r, sx[jj], sy[jj], sz[jj])) st[2] += 1; }
-                    float p;
-                    if (eval_p_kept(rr, sx[jj], sy[jj], sz[jj], p)) {
-                        // (with p = 0 the sums keep their bits, as in the forward, which skips)
-                        a[jj] = fmaf(p, sig, a[jj]);
-                        G[jj] = fmaf(p, gam, G[jj]);
-                        hit |= p != 0.0f;
+                if (pv.get(jj) != PV_DEAD) {
+                    CS cs;
+#pragma unroll
+                    for (int i = 0; i < CS::NM; ++i) {
+                        const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(srs, vm, jj * 64 * MB + 16 * i, 0);
+                        cs.m[i] = f32x4_t{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                                          __uint_as_float(v[3])};
                     }
+                    const u32x2_t e = __builtin_amdgcn_raw_buffer_load_b64(srs, ve, KC * 64 * MB + jj * 64 * 8, 0);
+                    if constexpr (CS::NX > 0) cs.x[0] = __uint_as_float(e[0]);
+                    a[jj] = __uint_as_float(e[1]);
+                    float g = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) {
+                        float gs;
+                        if constexpr (SPLIT) gs = c < 16 ? lgs[c * LGS_STRIDE + lane] : gS16;
+                        else gs = gS[c];
+                        g = fmaf(gs, cs.get(c), g);
+                    }
+                    G[jj] = g;
                 }
             }
-            if (wave_ballot(hit) == 0) {
-                // p = 0 for every lane and sample: the adjoint of k is 0 in this
-                // chunk, so pass 2 need not visit it
-                if (lane == 0) bm[k >> 5] &= ~(1u << (k & 31));
-            }
-        });
+        } else {
+            // ---- pass 1: a_j and G_j over the union, ascending id -----------
+            for_each_marked(bm, nw, lane, [&](int k) {
+                const cf_ptr r = X.rec_at(k);
+                Pinned<19> rr;
+                Pinned<CP> lg;
+                pin2(r, rr, X.template lgp_at<CP>(k), lg);
+                bool mem[KC];
+                pv.members(__float_as_uint(rr[R_GLO]), __float_as_uint(rr[R_GHI]), mem);
+                bool anym = false;
+#pragma unroll
+                for (int jj = 0; jj < KC; ++jj) anym |= mem[jj];
+                if (wave_ballot(anym) == 0) return;
+                const float sig = rr[15];
+                // gamma up front: the sums are then updated inside each sample's
+                // branch, and a culled pair costs no default value of p
+                const float gam = gamma_of(lg);
+                bool hit = false;
+#pragma unroll
+                for (int jj = 0; jj < KC; ++jj) {
+                    if (mem[jj]) {
+                        if (STATS) { st[1] += 1; if (pair_kept(r, sx[jj], sy[jj], sz[jj])) st[2] += 1; }
+                        float p;
+                        if (eval_p_kept(rr, sx[jj], sy[jj], sz[jj], p)) {
+                            // (with p = 0 the sums keep their bits, as in the forward, which skips)
+                            a[jj] = fmaf(p, sig, a[jj]);
+                            G[jj] = fmaf(p, gam, G[jj]);
+                            hit |= p != 0.0f;
+                        }
+                    }
+                }
+                if (wave_ballot(hit) == 0) {
+                    // p = 0 for every lane and sample: the adjoint of k is 0 in this
+                    // chunk, so pass 2 need not visit it
+                    if (lane == 0) bm[k >> 5] &= ~(1u << (k & 31));
+                }
+            });
+        }
 
         // ---- compositing and its adjoint (per lane) -------------------------
         float Tj[KC];
@@ -1203,6 +1308,10 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 const bool pres = (T > 0.0f) && (T >= kappa);
                 Tj[jj] = pres ? T : 0.0f;
                 if (pres) T = T * (1.0f - fminf(a[jj], 1.0f));
+                // (an absent sample's values are not the forward's: zero them,
+                // which leaves the recursion below as it is for finite ones)
+                a[jj] = pres ? a[jj] : 0.0f;
+                G[jj] = pres ? G[jj] : 0.0f;
             }
         }
 #pragma unroll
@@ -1835,6 +1944,20 @@ static Ctx make_ctx(const GridDev& g, const BatchDesc& d, const MarchDev& mr, co
     P.lam_s = P.lam_d = 0.0f;
     P.lcount = l.lcount; P.lpart = l.lpart;
     P.tile_stop = io.tile_stop;
+    P.stash_hdr = nullptr; P.stash_tab = nullptr; P.stash_pool = nullptr;
+    P.stash_slots = 0; P.stash_slot_floats = 0;
+    // (a call without checkpoints only rewrites the header, marking the stash
+    // as not its own)
+    if (io.stash && io.stash_len >= STASH_HEAD) {
+        P.stash_hdr = reinterpret_cast<int*>(io.stash);
+        const StashGeom sg = stash_geom(d, mr.L, mr.K);
+        if (mr.K > 0 && io.stash_len >= sg.pool_off) {
+            P.stash_tab = P.stash_hdr + sg.tab_off;
+            P.stash_pool = io.stash + sg.pool_off;
+            P.stash_slots = (int)std::min<int64_t>((io.stash_len - sg.pool_off) / sg.slot_floats, INT32_MAX);
+            P.stash_slot_floats = (int)sg.slot_floats;
+        }
+    }
     return P;
 }
 
@@ -1870,9 +1993,17 @@ static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
     prep_records<CP>(d, g, io, l, st);
     const int wpb = t.waves_per_block;
     Ctx P = P0;
+    // the stash serves only the primitive-major backward of this tuning
+    if (P.stash_tab && !(t.bwd_mode != 1 && bwd_primitive_major_ok(g, d.max_n, P.mr.K, wpb))) {
+        P.stash_tab = nullptr;
+        P.stash_pool = nullptr;
+    }
     if (P.tile_stop)
         hipLaunchKernelGGL(k_stop_header, dim3(1), dim3(64), 0, st, P.tile_stop, d.tile_w, P.mr.L, P.mr.K,
                            P.ckpt != nullptr && P.mr.K > 0 ? 1 : 0);
+    if (P.stash_hdr)
+        hipLaunchKernelGGL(k_stash_header, dim3(1), dim3(64), 0, st, P.stash_hdr, d.tile_w, P.mr.L, P.mr.K,
+                           P.ckpt != nullptr && P.stash_tab != nullptr ? 1 : 0, P.stash_slots);
     // the union walk tests membership on packed cells
     if (!bitmap_fits(d.max_n, wpb) || !cells_fit(g)) P.bitmap_words = 0;
     const size_t shm = (size_t)wpb * P.bitmap_words * sizeof(uint32_t);

@@ -73,7 +73,28 @@ struct BatchIO {
     const float* depth_label;
     float* loss;
     int32_t* tile_stop;       // nullable: [4 + total_tiles], header then one stop per tile
+    float* stash;             // nullable: per-sample forward values for the backward (StashGeom)
+    int64_t stash_len;        // floats of stash
 };
+
+// Layout of the per-sample stash of a forward with checkpoints (floats from
+// the start of the buffer): a header of STASH_HEAD int32 ([0] tile width,
+// [1] L, [2] K, [3] 1 once a forward with checkpoints wrote it, [4] slots that
+// forward asked for, [5] slots the buffer holds), the slot of every (global
+// tile, chunk) as int32 (-1: none), then the pool of slots.  A slot holds, for
+// the K samples of one tile's chunk and each of its 64 lanes, the density sum
+// a and the class sums s[0..CP) of the sample: [K][64][4 NM] floats (the
+// matrix-core class accumulators as they are in registers), then
+// [K][64][2] floats (s[CP-1] when CP = 4 NM + 1, else 0; then a).
+constexpr int STASH_HEAD = 16;
+struct StashGeom {
+    int64_t tab_off;      // int32 offset of the slot table
+    int64_t pool_off;     // float offset of the pool (256-byte aligned)
+    int64_t slot_floats;  // floats per slot
+    int nck;              // chunks per tile
+    int m_floats;         // 4 NM: class sums held in four-wide accumulators
+};
+StashGeom stash_geom(const BatchDesc& d, int L, int K);
 
 // Weights of the fused loss (Eq. eq:loss); nullptr = no loss epilogue.
 struct LossArgs {

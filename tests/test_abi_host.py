@@ -220,6 +220,7 @@ def _batch_io():
         setattr(io, name, FAKE)
     io.tile_stop_len = 1 << 40
     io.ckpt_len = 1 << 40
+    io.stash_len = 1 << 40
     return io
 
 
@@ -336,6 +337,44 @@ def test_march_kappa_outside_unit_interval_is_rejected(kappa):
     rc = lib.sq_render_fwd(ct.byref(_grid()), ct.byref(_index()), ct.byref(_prims()), ct.byref(_rays()), ct.byref(m),
                            FAKE, FAKE, None, FAKE, None, None, ct.byref(t), 0x100000, 1 << 30, None)
     assert rc == L.SQ_ERR_INVALID and "kappa" in lib.sq_last_error().decode()
+
+
+def test_stash_length_query_and_short_buffer():
+    """Header and slot table (16 + tiles x ceil(L/K) int32, rounded up to 64
+    floats), then K x 64 x (Q + 2) floats per slot, Q = the class count padded
+    to the matrix-core width (8 at C = 5); a buffer shorter than header and
+    table is refused before any launch, by forwards with checkpoints and the
+    backward; a forward without checkpoints needs the header only."""
+    lib = L.load()
+    b = _batch()          # L = 100, C = 5
+    for tw, tiles in ((8, 24), (16, 18), (4, 24)):
+        for K in (4, 8):
+            t = L.SqTuning(tw, 4, 0, 0, K)
+            n0 = lib.sq_batch_stash_len(ct.byref(b), ct.byref(t), 0)
+            nck = -(-100 // K)
+            assert n0 == -(-(16 + tiles * nck) // 64) * 64
+            assert lib.sq_batch_stash_len(ct.byref(b), ct.byref(t), 3) == n0 + 3 * K * 64 * (8 + 2)
+    t = L.SqTuning(8, 4, 0, 0, 8)
+    assert lib.sq_batch_stash_len(ct.byref(b), ct.byref(t), -1) == 0
+    assert lib.sq_batch_stash_len(ct.byref(b), ct.byref(L.SqTuning(8, 4, 0, 0, 5)), 0) == 0
+    assert lib.sq_batch_stash_len(ct.byref(b), ct.byref(t), 1 << 31) == 0
+    b17 = _batch(C=17)
+    n0 = lib.sq_batch_stash_len(ct.byref(b17), ct.byref(t), 0)
+    assert lib.sq_batch_stash_len(ct.byref(b17), ct.byref(t), 1) == n0 + 8 * 64 * (16 + 2)
+    io = _batch_io()
+    io.stash_len = lib.sq_batch_stash_len(ct.byref(b), ct.byref(t), 0) - 1
+    w = L.SqLossWeights(2.0, 0.05)
+    for call in (lambda: lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30, None),
+                 lambda: lib.sq_batch_render_bwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30, None),
+                 lambda: lib.sq_batch_render_fwd_loss(ct.byref(b), ct.byref(io), ct.byref(w), ct.byref(t), 0x100000,
+                                                      1 << 30, None),
+                 lambda: lib.sq_batch_step(ct.byref(b), ct.byref(io), ct.byref(t), 0x100000, 1 << 30, None)):
+        assert call() == L.SQ_ERR_CAPACITY
+        assert "stash" in lib.sq_last_error().decode()
+    io.ckpt = None
+    io.stash_len = 15
+    assert lib.sq_batch_render_fwd(ct.byref(b), ct.byref(io), None, ct.byref(t), 0x100000, 1 << 30,
+                                   None) == L.SQ_ERR_CAPACITY
 
 
 def test_tile_stop_length_query_and_short_buffer():

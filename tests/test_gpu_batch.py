@@ -3,6 +3,8 @@ camera counts in single launches (static and persistent tile scheduling), the
 hipGraph-captured step and the autotuner.  Each scene of a batch must match
 its own single-scene render (forward bit for bit: the same tile code runs) and
 the FP64 oracle."""
+import ctypes as ct
+
 import numpy as np
 import pytest
 
@@ -311,3 +313,173 @@ def test_tile_stops_used_and_ignored():
         ign = {k[2:]: o[k].cpu().numpy() for k in o if k.startswith("g_")}
         H.assert_grads_close({k[2:]: v.cpu().numpy() for k, v in used[i].items()}, ref, f"scene {i} stops used")
         H.assert_grads_close(ign, ref, f"scene {i} stops ignored")
+
+
+def _grads(b, n):
+    return [{k[2:]: v.cpu().numpy() for k, v in b.scene_outputs(i).items() if k.startswith("g_")} for i in range(n)]
+
+
+@pytest.mark.parametrize("tw,K", [(8, 4), (16, 8)])
+def test_stash_backward_matches_recompute_and_oracle(tw, K):
+    """A forward with checkpoints leaves a_j and the class sums in the stash;
+    the backward then skips its first evaluation of each chunk's pairs.  The
+    forward's outputs do not change (bit for bit), the slots asked for are one
+    per chunk each tile entered, and the gradients match the recomputing
+    backward and the oracle, with a full pool and with one that covers a
+    third of the chunks (the rest recomputed)."""
+    scenes = _small_batch(seed=97, ns=(30, 12, 40), sizes=((24, 16), (9, 7), (16, 16)))
+    b = _make_batch(scenes, K=K)
+    ups = _upstream(scenes, 98)
+    for i, (gd, gs) in enumerate(ups):
+        b.set_upstream(i, torch.from_numpy(gd).cuda(), torch.from_numpy(gs).cuda())
+    tune = api.Tuning(tw, 2, 2, 1, K)
+    b.build_index()
+    _say(f"stash: recompute, tile {tw}, chunk {K}")
+    b.render_fwd(tune)
+    b.render_bwd(tune)
+    torch.cuda.synchronize()
+    fwd0 = {k: b.buf[k].clone() for k in ("depth", "sem", "probs", "t_final", "ckpt")}
+    g0 = _grads(b, 3)
+    L = scenes[0].march.n_samples
+    stops = b.buf["tile_stop"][4:4 + b.buf["tile_stop"].numel() - 4].cpu().numpy()
+    _say("stash: header only, counting")
+    b.set_stash(0, tune)
+    b.render_fwd(tune)
+    torch.cuda.synchronize()
+    head = b.buf["stash"][:16].view(torch.int32).cpu().tolist()
+    demand = b.stash_demand()
+    assert head[:4] == [tw, L, K, 1] and head[5] == 0, head
+    n_tiles = int(lib_tiles(b, tw))
+    assert demand == int(np.sum(stops[:n_tiles] // K + 1)), (demand, n_tiles)
+    for slots, what in ((demand, "full pool"), (demand // 3, "a third")):
+        _say(f"stash: {what} ({slots} of {demand} slots)")
+        b.set_stash(slots, tune)
+        b.render_fwd(tune)
+        b.render_bwd(tune)
+        torch.cuda.synchronize()
+        for k, v in fwd0.items():
+            assert torch.equal(b.buf[k], v), (what, k)
+        h = b.buf["stash"][:16].view(torch.int32).cpu().tolist()
+        assert h[4] == demand and h[5] == slots, h
+        g = _grads(b, 3)
+        for i, sc in enumerate(scenes):
+            if not sc.prims.n:
+                continue
+            for k in g[i]:
+                np.testing.assert_allclose(g[i][k], g0[i][k], rtol=2e-4, atol=1e-5 * (np.abs(g0[i][k]).max() + 1e-30),
+                                           err_msg=f"{what} scene {i} {k}")
+            gd, gs = ups[i]
+            ref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, gd, gs)
+            H.assert_grads_close(g[i], ref, f"stash {what} scene {i}")
+
+
+def lib_tiles(b, tw):
+    """Tiles of the batch at tile width tw (the length of its stop table less the header)."""
+    from paper_2511_17361_amd import _lib as L
+    return L.load().sq_batch_tile_stop_len(ct.byref(b.c_batch), ct.byref(api.Tuning(tile_w=tw).c())) - 4
+
+
+def test_stash_of_another_tiling_or_of_a_plain_forward_is_ignored():
+    """A backward whose tiling differs from the stashing forward's, and one
+    after a forward without checkpoints (which marks the stash as not its
+    own), recompute; both give the oracle's gradients."""
+    scenes = _small_batch(seed=99, ns=(25, 18), sizes=((20, 12), (12, 12)))
+    b = _make_batch(scenes, K=4)
+    ups = _upstream(scenes, 100)
+    for i, (gd, gs) in enumerate(ups):
+        b.set_upstream(i, torch.from_numpy(gd).cuda(), torch.from_numpy(gs).cuda())
+    b.set_stash(4096)
+    b.build_index()
+    _say("stash ignored: other tiling")
+    b.render_fwd(api.Tuning(8, 2, 2, 1, 4))
+    b.render_bwd(api.Tuning(16, 2, 2, 1, 4))
+    torch.cuda.synchronize()
+    g = _grads(b, 2)
+    for i, sc in enumerate(scenes):
+        gd, gs = ups[i]
+        H.assert_grads_close(g[i], oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, gd, gs), f"other tiling {i}")
+    _say("stash marked by a forward without checkpoints")
+    ck = b.buf.pop("ckpt")
+    b.render_fwd(api.Tuning(8, 2, 2, 1, 4))
+    b.buf["ckpt"] = ck
+    torch.cuda.synchronize()
+    assert b.buf["stash"][:16].view(torch.int32)[3].item() == 0
+
+
+def test_graph_replays_with_stash_match_eager_step():
+    scenes = _small_batch(seed=101)
+    b = _make_batch(scenes, K=8)
+    for i, (gd, gs) in enumerate(_upstream(scenes, 3)):
+        b.set_upstream(i, torch.from_numpy(gd).cuda(), torch.from_numpy(gs).cuda())
+    tune = api.Tuning(8, 2, 2, 1, 8)
+    b.set_stash(0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.step(tune, stream=s)
+    torch.cuda.synchronize()
+    b.set_stash(b.stash_demand())
+    with torch.cuda.stream(s):
+        b.step(tune, stream=s)
+    torch.cuda.synchronize()
+    eager = {k: b.buf[k].clone() for k in ("depth", "sem", "t_final", "ckpt", "g_means", "g_logits", "g_opacity", "g_eps")}
+    # (the checkpoint buffer is sized for chunk 4; chunk 8 writes its first half)
+    used = -(-scenes[0].march.n_samples // 8) * b.n_rays
+    b.capture(tune, stream=s)
+    for rep in range(3):
+        for k in eager:
+            b.buf[k].fill_(-7.0)
+        b.buf["stash"][16:].fill_(float("nan"))
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        b.replay(stream=s)
+        torch.cuda.synchronize()
+        for k in ("depth", "sem", "t_final", "ckpt"):
+            n = used if k == "ckpt" else None
+            assert torch.equal(eager[k][:n], b.buf[k][:n]), (rep, k)
+        for k in ("g_means", "g_logits", "g_opacity", "g_eps"):
+            torch.testing.assert_close(b.buf[k], eager[k], rtol=1e-4, atol=1e-5)
+        del junk
+    b.release_graph()
+
+
+def test_bench_workload_step_with_stash_on_sampled_rays(bench_workload):
+    """The bench's workload with the stash sized by a first forward, through a
+    captured step replay, against the oracle on 400 rays with upstream
+    gradients (the rest zero)."""
+    sc, index = bench_workload
+    C = sc.prims.n_classes
+    rng = np.random.default_rng(45)
+    ids = rng.choice(sc.rays.n_rays, 400, replace=False)
+    g_d = np.zeros(sc.rays.n_rays, np.float32)
+    g_s = np.zeros((sc.rays.n_rays, C), np.float32)
+    g_d[ids] = rng.standard_normal(ids.size).astype(np.float32)
+    g_s[ids] = rng.standard_normal((ids.size, C)).astype(np.float32)
+    cams, Hh, Ww = sc.rays.shape
+    b = _make_batch([sc], K=8)
+    b.set_upstream(0, torch.from_numpy(g_d.reshape(cams, Hh, Ww)).cuda(),
+                   torch.from_numpy(g_s.reshape(cams, Hh, Ww, C).transpose(0, 3, 1, 2).copy()).cuda())
+    tune = api.Tuning(16, 2, 0, 1, 8)
+    _say("bench workload with stash: sizing forward")
+    b.set_stash(0)
+    b.build_index()
+    b.render_fwd(tune)
+    torch.cuda.synchronize()
+    demand = b.stash_demand()
+    assert demand > 0
+    b.set_stash(demand)
+    _say(f"bench workload with stash: {demand} slots, {b.buf['stash'].numel() * 4 / 2**30:.2f} GiB; step replay")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.step(tune, stream=s)
+    torch.cuda.synchronize()
+    b.capture(tune, stream=s)
+    b.replay(stream=s)
+    torch.cuda.synchronize()
+    b.release_graph()
+    assert b.stash_demand() == demand
+    out = {k: v.cpu().numpy() for k, v in b.scene_outputs(0).items()}
+    ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march, index=index, ray_ids=ids)
+    H.assert_depth_close(out["depth"].reshape(-1)[ids], ref["depth"], "bench workload, stash")
+    gref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d[ids], g_s[ids], index=index, ray_ids=ids)
+    got = {k: out["g_" + k] for k in ("means", "quats", "scales", "eps", "opacity", "logits")}
+    H.assert_grads_close(got, gref, "bench workload, stash")
