@@ -1369,6 +1369,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                 for (int i = 0; i < VR; ++i) x[i] = 0.0f;
             }
             float om = 0.0f;          // sum_j w_j p_jk
+            bool anyk = false;
 #pragma unroll
             for (int jj = 0; jj < KC; ++jj) {
                 if (mem[jj]) {
@@ -1378,6 +1379,7 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                     if (STATS) { st[4] += 1; if (kept) st[5] += 1; }
                     // (a kept pair whose p underflows to 0 adds exactly 0)
                     if (kept) {
+                        anyk = true;
                         const float da = a[jj], w = G[jj];
                         const float dfn = ev.p * fmaf(da, sig, w * gam);
                         pair_adjoint<VR>(rr, ev, dd, dfn, da, x);
@@ -1385,10 +1387,10 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                     }
                 }
             }
-            // (no test for a visit without a kept pair: pass 1 dropped every
-            // primitive with p = 0 throughout the chunk, so such visits are rare,
-            // and tracking the flag through the eight branches costs more scalar
-            // instructions per visit than their epilogues of zeros)
+            // a visit that kept no pair adds nothing: no reduction, no atomics
+            // (with the stash, pass 2 also meets the primitives that pass 1
+            // would have dropped for p = 0 throughout the chunk)
+            if (wave_ballot(anyk) == 0) return;
             if constexpr (SPLIT) {
                 // classes 0..15: lane (q, c) = (lane / 16, lane % 16)
                 float* omr = lgs + 16 * LGS_STRIDE;
