@@ -2,9 +2,9 @@
 """Benchmark of the superquadric renderer hot path on one MI355X.
 
 A step is one pass of the whole hot path over one synthetic batch: index build
-(sq_build_index), differentiable forward with transmittance checkpoints
-(sq_render_fwd) and backward (sq_render_bwd) for fixed random upstream
-gradients.  Default workload: 6 cameras x 900 x 1600 rays, 25,600
+(sq_build_index), differentiable forward with transmittance checkpoints and
+the per-sample stash (sq_batch_io.stash; --no-stash leaves it out) and backward
+(sq_render_bwd) for fixed random upstream gradients.  Default workload: 6 cameras x 900 x 1600 rays, 25,600
 superquadrics (40% in 64 dense blobs), 200 samples per ray in [0.1, 50] m,
 17 classes, 200x200x16 grid at 0.4 m, N_v = 5.
 
@@ -57,14 +57,18 @@ def flops_fwd(st, C):
     return 24 * listed + (16 + 2 * C) * evaluated + (23 + 7 + 2 * C) * samples
 
 
-def flops_bwd(fst, C):
+def flops_bwd(fst, C, stash=False):
     """Algorithmic FLOPs of the backward over the method's own (sample,
     primitive) pairs, the forward's counts: the recompute and the adjoint each
     cover every listed pair of every live sample once.  Work the kernel skips
     because it is provably zero (samples past a ray's end in pass 1, primitives
-    with p = 0 throughout a chunk in pass 2) is neither added nor removed."""
-    recompute = 24 * fst["listed"] + (20 + 2 * C) * fst["evaluated"] + (23 + 7 + 2 * C) * fst["samples"]
+    with p = 0 throughout a chunk in pass 2) is neither added nor removed.
+    With the stash there is no recompute: each live sample's G_j = <g_S, s_j>
+    (C FMAs) takes its place."""
     adjoint = 24 * fst["listed"] + (112 + 3 * C) * fst["evaluated"] + (23 + 10) * fst["samples"]
+    if stash:
+        return adjoint + 2 * C * fst["samples"]
+    recompute = 24 * fst["listed"] + (20 + 2 * C) * fst["evaluated"] + (23 + 7 + 2 * C) * fst["samples"]
     return recompute + adjoint
 
 
@@ -89,19 +93,23 @@ def recorded_profile():
     return rec
 
 
-def stage_bytes(R, C, L, K, N, V, E, probs=True, ckpt=True):
+def stage_bytes(R, C, L, K, N, V, E, probs=True, ckpt=True, stash_samples=0):
     """Algorithmic HBM bytes of each stage (inputs read once, outputs written
     once; lists, records and per-sample state that stay on chip are not
     counted):
       index:    means 12 N, counts and offsets 4 V each, ids 4 E;
       forward:  rays 24 R, primitives 120 N, depth and t_final 4 R each, sem
-                4 C R, probs 4 C R, checkpoints 4 ceil(L/K) R;
+                4 C R, probs 4 C R, checkpoints 4 ceil(L/K) R, and with the
+                stash 4 (Q + 2) per live sample (Q: C padded to 4, 8, 16, 32);
       backward: rays 24 R, primitives 120 N, g_D 4 R, g_S 4 C R, checkpoints
-                4 ceil(L/K) R, gradients 4 (13 + C) N."""
+                4 ceil(L/K) R, gradients 4 (13 + C) N, and the stash read back."""
     nck = -(-L // K)
+    cp = api_cp(C)
+    q = cp // 16 * 16 if cp >= 16 else cp
+    st = 4 * (q + 2) * stash_samples
     idx = 12 * N + 8 * V + 4 * E
-    fwd = 24 * R + 120 * N + 8 * R + 4 * C * R * (2 if probs else 1) + (4 * nck * R if ckpt else 0)
-    bwd = 24 * R + 120 * N + 4 * R + 4 * C * R + 4 * nck * R + 4 * (13 + C) * N
+    fwd = 24 * R + 120 * N + 8 * R + 4 * C * R * (2 if probs else 1) + (4 * nck * R if ckpt else 0) + st
+    bwd = 24 * R + 120 * N + 4 * R + 4 * C * R + 4 * nck * R + 4 * (13 + C) * N + st
     return dict(index=idx, fwd=fwd, bwd=bwd)
 
 
@@ -129,6 +137,8 @@ def parse():
     ap.add_argument("--cpu-procs", type=int, default=0, help="CPU-baseline worker processes (0: every core, <= 16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--no-stash", action="store_true",
+                    help="no per-sample stash: the backward recomputes each chunk's a_j and G_j")
     ap.add_argument("--no-autotune", action="store_true",
                     help="run the tuning given by --tile-w/--wpb/--ckpt-every instead of timing the default "
                          "candidates first and running the fastest")
@@ -245,7 +255,24 @@ def sq_major_ab(dev, steps, K=4):
                 atomics_ms=t_atomic, sq_major_ms=t_sqm)
 
 
-def batched_8_scenes(dev, steps, warmup):
+def size_stash(batch, tune, stream, headroom=1.25):
+    """Give `batch` a per-sample stash: a forward with only the header and
+    slot table counts the slots it asks for, and the pool gets that many
+    times `headroom` (for every tiling the autotuner may pick; a chunk left
+    without a slot is recomputed)."""
+    import torch
+    batch.set_stash(0)
+    with torch.cuda.stream(stream):
+        batch.build_index(stream=stream)
+        batch.render_fwd(tune, stream=stream)
+    torch.cuda.synchronize()
+    demand = batch.stash_demand()
+    slots = int(demand * headroom) + 64
+    batch.set_stash(slots)
+    return dict(demand=demand, slots=slots, gib=batch.buf["stash"].numel() * 4 / 2 ** 30)
+
+
+def batched_8_scenes(dev, steps, warmup, use_stash=True):
     """The batched training step over the 8 scenes of uneven size (2k .. 25.6k
     superquadrics, 94k in all; 6 cameras x 352x200 rays each, L = 100), with the
     tuning chosen by the autotuner, captured once and replayed."""
@@ -265,6 +292,7 @@ def batched_8_scenes(dev, steps, warmup):
         gd, gs = synth.upstream_grads(rng, s.rays, s.prims.n_classes)
         batch.set_upstream(i, torch.from_numpy(gd).to(dev), torch.from_numpy(gs).to(dev))
     stream = torch.cuda.Stream(device=dev)
+    stash = size_stash(batch, api.Tuning(8, 2, 0, 1, 4), stream) if use_stash else None
     with torch.cuda.stream(stream):
         tune, _ = batch.autotune(api.default_candidates(), reps=1, stream=stream)
     torch.cuda.synchronize()
@@ -290,7 +318,7 @@ def batched_8_scenes(dev, steps, warmup):
                 ray_samples_per_s=samples / (ms / 1e3), listed_pairs=listed,
                 rays_per_s=batch.n_rays / (ms / 1e3), pairs_per_s=listed / (ms / 1e3),
                 tuning=dict(tile_w=tune.tile_w, waves_per_block=tune.waves_per_block, bwd_mode=tune.bwd_mode,
-                            persistent=tune.persistent, chunk=tune.chunk))
+                            persistent=tune.persistent, chunk=tune.chunk), stash=stash)
 
 
 def paper_setting(dev, steps):
@@ -371,6 +399,8 @@ def main():
     stream = torch.cuda.Stream(device=dev)
 
     tune = api.Tuning(args.tile_w, args.wpb, args.bwd_mode, 1, args.ckpt_every)
+    # the per-sample stash, sized by the slots a first forward asks for
+    stash = None if args.no_stash else size_stash(batch, tune, stream)
     tuned_ms = None
     cands = api.default_candidates()
     if not args.no_autotune:
@@ -520,7 +550,13 @@ def main():
                 f"({'/'.join(str(s.prims.n) for s in scenes)}), {sc0.rays.shape[0]} cameras x "
                 f"{sc0.rays.shape[2]}x{sc0.rays.shape[1]} rays per scene, L={Ls} in [{sc0.march.t_near}, "
                 f"{sc0.march.t_far}] m, C={C}, grid {'x'.join(map(str, sc0.grid.dims))} at {sc0.grid.voxel} m, "
-                f"N_v={sc0.grid.nv}; step = index + forward(checkpoints) + backward, one hipGraph replay")
+                f"N_v={sc0.grid.nv}; step = index + forward(checkpoints"
+                f"{', per-sample stash' if stash else ''}) + backward, one hipGraph replay")
+    if stash is not None:
+        # the slots the last forward (the chosen tuning) asked for against the pool
+        hdr = batch.buf["stash"][:16].view(torch.int32).cpu().tolist()
+        stash["covered"] = hdr[4] <= hdr[5]
+        stash["demand_last"] = hdr[4]
     result = {
         "metric": METRIC,
         "value": R * Ls / (ms_step / 1e3),
@@ -539,7 +575,7 @@ def main():
                    "tuning": dict(tile_w=tune.tile_w, waves_per_block=tune.waves_per_block,
                                   bwd_mode=tune.bwd_mode, persistent=tune.persistent,
                                   chunk=tune.chunk or args.ckpt_every),
-                   "autotuned": not args.no_autotune},
+                   "autotuned": not args.no_autotune, "stash": stash},
         "fwd_ray_samples_per_s": R * Ls / (t_fwd / 1e3),
         "plain_fwd_ray_samples_per_s": R * Ls / (t_plain / 1e3),
         "rays_per_s_fwd_bwd": R / (ms_step / 1e3),
@@ -574,7 +610,8 @@ def main():
         result["fwd_tflops"] = flops_fwd(fst, C) / (t_fwd / 1e3) / 1e12
         result["fwd_roofline_frac"] = result["fwd_tflops"] / VALU_PEAK_TFLOPS
         result["fwd_roofline_frac_nonpacked"] = result["fwd_tflops"] / VALU_NONPACKED_TFLOPS
-        f_bwd = flops_bwd(fst, C)
+        stashed = stash is not None and stash["covered"]
+        f_bwd = flops_bwd(fst, C, stash=stashed)
         ach = f_bwd / (t_bwd / 1e3) / 1e12
         kname = f"sqr::k_render_bwd_km<{api_cp(C)}, {K}, false, {'true' if tune.persistent else 'false'}>"
         prof = recorded_profile()
@@ -588,7 +625,8 @@ def main():
         # every form of the path at this workload: rays/s, ray-samples/s, pairs/s (the
         # method's listed (sample, primitive) pairs), algorithmic HBM GB/s and its fraction
         N = sum(s_.prims.n for s_ in scenes)
-        sb = stage_bytes(R, C, Ls, K, N, grid.n_voxels * len(scenes), sum(E))
+        sb = stage_bytes(R, C, Ls, K, N, grid.n_voxels * len(scenes), sum(E),
+                         stash_samples=fst["samples"] if stashed else 0)
         sbp = stage_bytes(R, C, Ls, K, N, grid.n_voxels * len(scenes), sum(E), ckpt=False)
         P = fst["listed"]
         result["forms"] = {
@@ -609,7 +647,7 @@ def main():
                             if k.startswith("sqr::k_render") or k.startswith("sqr::k_tile_lists")}}
 
     result["sq_major_ab"] = sq_major_ab(dev, args.steps)
-    result["batched_8_scenes"] = batched_8_scenes(dev, args.steps, args.warmup)
+    result["batched_8_scenes"] = batched_8_scenes(dev, args.steps, args.warmup, use_stash=not args.no_stash)
     result["paper_setting"] = paper_setting(dev, args.steps)
 
     if args.calib_copy_mb > 0:

@@ -1234,28 +1234,44 @@ __device__ __forceinline__ void bwd_km_tile(const Ctx& P, int s, int tile, uint3
                                                   0x00020000);
             constexpr int MB = 4 * CS::NM * (int)sizeof(float);     // class-sum bytes per lane and sample
             const uint32_t vm = (uint32_t)lane * MB, ve = (uint32_t)lane * 8u;
+            // two samples per round trip (one at 32 classes, where two would
+            // spill), loaded by every lane (the slot is in bounds whatever the
+            // lane holds); absent samples are masked
+            constexpr int NS = CP <= 17 ? 2 : 1;
 #pragma unroll
-            for (int jj = 0; jj < KC; ++jj) {
-                if (pv.get(jj) != PV_DEAD) {
-                    CS cs;
+            for (int j2 = 0; j2 < KC; j2 += NS) {
+                __builtin_amdgcn_sched_barrier(0);
+                CS cs[NS];
+                float ea[NS];
+#pragma unroll
+                for (int h = 0; h < NS; ++h) {
+                    const int jj = j2 + h;
 #pragma unroll
                     for (int i = 0; i < CS::NM; ++i) {
                         const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(srs, vm, jj * 64 * MB + 16 * i, 0);
-                        cs.m[i] = f32x4_t{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
-                                          __uint_as_float(v[3])};
+                        cs[h].m[i] = f32x4_t{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                                             __uint_as_float(v[3])};
                     }
                     const u32x2_t e = __builtin_amdgcn_raw_buffer_load_b64(srs, ve, KC * 64 * MB + jj * 64 * 8, 0);
-                    if constexpr (CS::NX > 0) cs.x[0] = __uint_as_float(e[0]);
-                    a[jj] = __uint_as_float(e[1]);
-                    float g = 0.0f;
+                    if constexpr (CS::NX > 0) cs[h].x[0] = __uint_as_float(e[0]);
+                    ea[h] = __uint_as_float(e[1]);
+                }
+                float g[NS];
 #pragma unroll
-                    for (int c = 0; c < CP; ++c) {
-                        float gs;
-                        if constexpr (SPLIT) gs = c < 16 ? lgs[c * LGS_STRIDE + lane] : gS16;
-                        else gs = gS[c];
-                        g = fmaf(gs, cs.get(c), g);
-                    }
-                    G[jj] = g;
+                for (int h = 0; h < NS; ++h) g[h] = 0.0f;
+#pragma unroll
+                for (int c = 0; c < CP; ++c) {
+                    float gs;
+                    if constexpr (SPLIT) gs = c < 16 ? lgs[c * LGS_STRIDE + lane] : gS16;
+                    else gs = gS[c];
+#pragma unroll
+                    for (int h = 0; h < NS; ++h) g[h] = fmaf(gs, cs[h].get(c), g[h]);
+                }
+#pragma unroll
+                for (int h = 0; h < NS; ++h) {
+                    const bool live = pv.get(j2 + h) != PV_DEAD;
+                    a[j2 + h] = live ? ea[h] : 0.0f;
+                    G[j2 + h] = live ? g[h] : 0.0f;
                 }
             }
         } else {
