@@ -58,11 +58,11 @@ StashGeom stash_geom(const BatchDesc& d, int L, int K) {
 }
 
 // Occupancy targets (waves per SIMD) that the register allocator must meet.
-// At 6 the persistent forward with checkpoints spills a few per-tile pointers
-// (stored at the tile's start, reloaded for its epilogue), which costs less
-// than the wave it buys.
+// The persistent forward with checkpoints runs at 5: at 6 it spills a few
+// per-tile pointers, and its scratch reloads then also wait on the stash
+// stores that precede them (one vector-memory counter, in order).
 #define FWD_WPE(CP, CKPT, STATS, PERSIST) \
-    ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : (!(CKPT) || (PERSIST)) ? 6 : 4)
+    ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : !(CKPT) ? 6 : (PERSIST) ? 5 : 4)
 #define BWD_WPE(CP, KC) ((CP) <= 17 ? 4 : 3)
 
 // Kernel parameters shared by every render kernel.
