@@ -259,6 +259,105 @@ def render_fwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt_every: 
     return out
 
 
+class StashPool:
+    """The per-sample stash (sq_batch_io.stash) of the one-scene training
+    path (render_train_fwd): sized on first use for a workload (scene shape,
+    classes, march, tiling) by the slots its forward asks for, times
+    `headroom`, and reused by later calls of that workload.  Chunks beyond
+    the pool are recomputed by the backward, so a workload that grows stays
+    correct."""
+
+    def __init__(self, headroom: float = 1.25):
+        self.headroom = float(headroom)
+        self.buf: Optional[torch.Tensor] = None
+        self.key = None
+
+    def demand(self) -> int:
+        """Slots the last forward asked for (synchronises)."""
+        return 0 if self.buf is None else int(self.buf[:L.SQ_STASH_HEAD].view(torch.int32)[4].item())
+
+
+def _one_scene_io(st, g_depth=None, g_sem=None, grads=None) -> L.SqBatchIO:
+    io = L.SqBatchIO()
+    p, r, ix = st["prims"], st["rays"], st["index"]
+    for k in ("means", "quats", "scales", "eps", "opacity", "logits"):
+        setattr(io, k, _ptr(getattr(p, k)))
+    io.origins, io.dirs = _ptr(r.origins), _ptr(r.dirs)
+    io.counts, io.offsets, io.ids, io.totals = _ptr(ix.counts), _ptr(ix.offsets), _ptr(ix.ids), _ptr(ix.total)
+    for k in ("depth", "sem", "t_final", "ckpt", "tile_stop"):
+        setattr(io, k, _ptr(st[k]))
+    io.tile_stop_len = int(st["tile_stop"].numel())
+    io.ckpt_len = int(st["ckpt"].numel())
+    pool = st["stash"]
+    if pool is not None and pool.buf is not None:
+        io.stash, io.stash_len = _ptr(pool.buf), int(pool.buf.numel())
+    io.g_depth, io.g_sem = _ptr(g_depth), _ptr(g_sem)
+    if grads is not None:
+        for k, v in grads.items():
+            setattr(io, "g_" + k, _ptr(v))
+    return io
+
+
+def render_train_fwd(grid, index: Index, prims: Prims, rays: Rays, march, ckpt_every: int = 8,
+                     tuning: Optional[Tuning] = None, stash: Optional[StashPool] = None, stream=None) -> dict:
+    """The differentiable forward of one scene through the batched ABI, on the
+    caller's tensors (no copies): depth [cams,H,W], sem [cams,C,H,W], t_final,
+    the checkpoints and the per-tile stops, and with a StashPool the
+    per-sample stash.  Returns the state render_train_bwd takes."""
+    lib = L.load()
+    grid, march = Grid.of(grid), March.of(march)
+    dev = prims.means.device
+    t = (tuning or Tuning()).c()
+    b = L.SqBatch()
+    b.n_scenes, b.n_classes = 1, prims.n_classes
+    b.grid, b.march = grid.c(), march.c(ckpt_every)
+    cams, H, W = rays.shape
+    C, R = prims.n_classes, cams * H * W
+    sc = b.scenes[0]
+    sc.n_prims, sc.n_cams, sc.height, sc.width, sc.index_capacity = prims.n, cams, H, W, index.capacity
+    nck = -(-march.n_samples // ckpt_every)
+    st = dict(batch=b, tuning=t, index=index, prims=prims, rays=rays, stash=stash,
+              depth=torch.empty((cams, H, W), device=dev), sem=torch.empty((cams, C, H, W), device=dev),
+              t_final=torch.empty((cams, H, W), device=dev), ckpt=torch.empty((nck, R), device=dev),
+              tile_stop=torch.empty(int(lib.sq_batch_tile_stop_len(ct.byref(b), ct.byref(t))), dtype=torch.int32,
+                                    device=dev),
+              ws=_workspace(lib.sq_batch_workspace(ct.byref(b)), dev), stream=stream)
+
+    def run():
+        L.check(lib.sq_batch_render_fwd(ct.byref(b), ct.byref(_one_scene_io(st)), None, ct.byref(t),
+                                        _ptr(st["ws"]), st["ws"].numel(), _stream_handle(stream)))
+
+    if stash is not None:
+        key = (cams, H, W, C, march.n_samples, ckpt_every, t.tile_w)
+        if stash.buf is None or stash.key != key:
+            # size the pool: a forward against the header and slot table alone counts the slots
+            n0 = int(lib.sq_batch_stash_len(ct.byref(b), ct.byref(t), 0))
+            if n0 <= 0:
+                raise ValueError("no stash layout for this call (chunk must be 4, 8 or 16)")
+            stash.buf, stash.key = torch.zeros(n0, dtype=torch.float32, device=dev), key
+            run()
+            slots = int(stash.demand() * stash.headroom) + 16
+            stash.buf = torch.zeros(int(lib.sq_batch_stash_len(ct.byref(b), ct.byref(t), slots)),
+                                    dtype=torch.float32, device=dev)
+    run()
+    return st
+
+
+def render_train_bwd(st: dict, g_depth: Optional[torch.Tensor], g_sem: Optional[torch.Tensor]) -> dict:
+    """The backward of render_train_fwd's render (same checkpoints, stops and
+    stash): gradients of sum(g_depth*depth) + sum(g_sem*sem) w.r.t. the
+    primitives."""
+    lib = L.load()
+    prims = st["prims"]
+    out = {k: torch.empty_like(getattr(prims, k)) for k in ("means", "quats", "scales", "eps", "opacity", "logits")}
+    gd = None if g_depth is None else _f32(g_depth, "g_depth")
+    gs = None if g_sem is None else _f32(g_sem, "g_sem")
+    L.check(lib.sq_batch_render_bwd(ct.byref(st["batch"]), ct.byref(_one_scene_io(st, gd, gs, out)), None,
+                                    ct.byref(st["tuning"]), _ptr(st["ws"]), st["ws"].numel(),
+                                    _stream_handle(st["stream"])))
+    return out
+
+
 def render_fwd_noalloc(grid, index: Index, prims: Prims, rays: Rays, march, ckpt_every: int = 0,
                        probs: bool = True, tuning: Optional[Tuning] = None, stream=None,
                        out: Optional[dict] = None) -> dict:

@@ -27,11 +27,11 @@ def _leaves(sc):
             for k in NAMES}
 
 
-def _render(sc, p, ckpt_every=8):
+def _render(sc, p, ckpt_every=8, stash=None):
     rays = api.Rays.from_numpy(sc.rays)
     return autograd.render(p["means"], p["quats"], p["scales"], p["eps"], p["opacity"], p["logits"],
                            rays.origins, rays.dirs, api.Grid.of(sc.grid), api.March.of(sc.march),
-                           ckpt_every=ckpt_every)
+                           ckpt_every=ckpt_every, stash=stash)
 
 
 def _softmax(sem):
@@ -93,3 +93,28 @@ def test_autograd_composes_with_a_reparametrisation():
     got = {k: p[k].grad.cpu().numpy() for k in NAMES if k != "scales"}
     got["scales"] = log_s.grad.cpu().numpy()
     H.assert_grads_close(got, want, "autograd exp(log s)")
+
+
+@pytest.mark.parametrize("ckpt_every", [4, 8])
+def test_autograd_with_a_stash_pool_over_two_steps(ckpt_every):
+    """The same render and loss with an api.StashPool: the first step sizes
+    the pool (a forward that counts the slots, then the pool), the second
+    reuses it; both steps' forward and gradients match the oracle, and the
+    second step asks for no more slots than the pool holds."""
+    sc = synth.config(0)
+    g_d, g_s = synth.upstream_grads(np.random.default_rng(13), sc.rays, sc.prims.n_classes)
+    pool = api.StashPool()
+    ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march)
+    ref_g = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    for step in range(2):
+        _say("autograd with a stash pool, K =", ckpt_every, "step", step)
+        p = _leaves(sc)
+        depth, sem = _render(sc, p, ckpt_every, stash=pool)
+        loss = (depth * torch.from_numpy(g_d).cuda()).sum() + (sem * torch.from_numpy(g_s).cuda()).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        H.assert_depth_close(depth.detach().cpu().numpy(), ref["depth"], f"autograd stash step {step}")
+        H.assert_probs_close(_softmax(sem.detach().cpu().numpy()), ref["probs"], f"autograd stash step {step}")
+        H.assert_grads_close({k: p[k].grad.cpu().numpy() for k in NAMES}, ref_g, f"autograd stash step {step}")
+    head = pool.buf[:16].view(torch.int32).cpu().tolist()
+    assert head[3] == 1 and 0 < head[4] <= head[5], head
