@@ -106,3 +106,33 @@ def test_kappa_config1_sampled_rays():
     out, _ = H.run_fwd(sc, ckpt_every=4)
     ids = np.random.default_rng(5).choice(sc.rays.n_rays, 2000, replace=False)
     _check_fwd(sc, out, "cfg1 kappa", ray_ids=ids)
+
+
+@pytest.mark.parametrize("K", [4, 8])
+def test_kappa_backward_with_the_stash_matches_oracle(K):
+    """Early termination with the per-sample stash (the one-scene training
+    path with an api.StashPool): the backward's transmittance recursion from
+    the stashed a_j stops where the forward stopped; gradients on the rays
+    clear of the kappa boundary match the oracle."""
+    _say("kappa bwd with the stash", K)
+    sc = _kappa_scene(random_scene(94, n=25, n_classes=4, nv=4, width=29, height=17, n_samples=37, opacity_hi=0.9,
+                                   dims=(16, 16, 8), voxel=0.5, lo=(-4.0, -4.0, -2.0), t_far=7.0), 2e-2, K)
+    ref = oracle.render(sc.grid, sc.prims, sc.rays, sc.march)
+    clear = ref["kappa_margin"] > CLEAR
+    rng = np.random.default_rng(10 + K)
+    g_d, g_s = synth.upstream_grads(rng, sc.rays, sc.prims.n_classes)
+    g_d = np.where(clear, g_d, 0.0).astype(np.float32)
+    g_s = np.where(clear[:, None], g_s, 0.0).astype(np.float32)
+    grid, prims, rays, march = H.gpu_scene(sc)
+    idx = api.build_index(grid, prims)
+    pool = api.StashPool()
+    st = api.render_train_fwd(grid, idx, prims, rays, march, ckpt_every=K, tuning=api.Tuning(8, 4, 2, 1, K),
+                              stash=pool)
+    g = api.render_train_bwd(st, torch.from_numpy(g_d).cuda(), torch.from_numpy(g_s).cuda())
+    torch.cuda.synchronize()
+    head = pool.buf[:16].view(torch.int32).cpu().tolist()
+    assert head[3] == 1 and 0 < head[4] <= head[5], head
+    gref = oracle.render_grad(sc.grid, sc.prims, sc.rays, sc.march, g_d, g_s)
+    H.assert_grads_close({k: v.cpu().numpy() for k, v in g.items()}, gref, f"kappa with stash K{K}")
+    tf = st["t_final"].cpu().numpy().reshape(-1)
+    assert np.sum((tf > 0) & (tf < 2e-2)) > 0
