@@ -442,7 +442,8 @@ def test_graph_replays_with_stash_match_eager_step():
     b.release_graph()
 
 
-def test_bench_workload_step_with_stash_on_sampled_rays(bench_workload):
+@pytest.mark.parametrize("tw,wpb,K", BENCH_TUNINGS)
+def test_bench_workload_step_with_stash_on_sampled_rays(bench_workload, tw, wpb, K):
     """The bench's workload with the stash sized by a first forward, through a
     captured step replay, against the oracle on 400 rays with upstream
     gradients (the rest zero)."""
@@ -455,11 +456,11 @@ def test_bench_workload_step_with_stash_on_sampled_rays(bench_workload):
     g_d[ids] = rng.standard_normal(ids.size).astype(np.float32)
     g_s[ids] = rng.standard_normal((ids.size, C)).astype(np.float32)
     cams, Hh, Ww = sc.rays.shape
-    b = _make_batch([sc], K=8)
+    b = _make_batch([sc], K=K)
     b.set_upstream(0, torch.from_numpy(g_d.reshape(cams, Hh, Ww)).cuda(),
                    torch.from_numpy(g_s.reshape(cams, Hh, Ww, C).transpose(0, 3, 1, 2).copy()).cuda())
-    tune = api.Tuning(16, 2, 0, 1, 8)
-    _say("bench workload with stash: sizing forward")
+    tune = api.Tuning(tw, wpb, 0, 1, K)
+    _say(f"bench workload with stash, tile {tw}, {wpb} waves per block, chunk {K}: sizing forward")
     b.set_stash(0)
     b.build_index()
     b.render_fwd(tune)
