@@ -58,11 +58,13 @@ StashGeom stash_geom(const BatchDesc& d, int L, int K) {
 }
 
 // Occupancy targets (waves per SIMD) that the register allocator must meet.
-// The persistent forward with checkpoints runs at 5: at 6 it spills a few
-// per-tile pointers, and its scratch reloads then also wait on the stash
-// stores that precede them (one vector-memory counter, in order).
-#define FWD_WPE(CP, CKPT, STATS, PERSIST) \
-    ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : !(CKPT) ? 6 : (PERSIST) ? 5 : 4)
+// The persistent forward with checkpoints runs at 6, where it spills a few
+// per-tile pointers (stored at the tile's start, reloaded for its epilogue),
+// which costs less than the wave it buys; the one that writes the stash runs
+// at 5, where their scratch reloads no longer wait on the stash stores ahead
+// of them (one vector-memory counter, in order).
+#define FWD_WPE(CP, CKPT, STATS, PERSIST, STASH) \
+    ((CP) <= 8 ? 6 : (CP) > 17 ? 3 : (STATS) ? 4 : !(CKPT) ? 6 : (PERSIST) ? ((STASH) ? 5 : 6) : 4)
 #define BWD_WPE(CP, KC) ((CP) <= 17 ? 4 : 3)
 
 // Kernel parameters shared by every render kernel.
@@ -416,7 +418,7 @@ __device__ __forceinline__ void for_each_marked(uint32_t* bm, int nw, int lane, 
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-template <int CP, bool CKPT, bool STATS, bool LOSS>
+template <int CP, bool CKPT, bool STATS, bool LOSS, bool STASH>
 __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t* bm) {
     const SceneDev& S = P.desc->s[s];
     const RayLane rl = setup_lane(P, S, tile);
@@ -433,7 +435,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
     static_assert(CS::NX <= 1, "the stash holds at most one class beyond the four-wide accumulators");
     // the stash (forward with checkpoints): each chunk the tile enters takes a
     // slot of the pool, where the chunk's samples leave a and their class sums
-    int* const stab = (CKPT && P.stash_tab) ? P.stash_tab + (int64_t)(S.tile_off + tile) * nck : nullptr;
+    int* const stab = (CKPT && STASH && P.stash_tab) ? P.stash_tab + (int64_t)(S.tile_off + tile) * nck : nullptr;
     int stash_slot = -1;
 
     float T = rl.valid ? 1.0f : 0.0f;
@@ -561,7 +563,7 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
                     pend = pend && !mine;
                 }
             }
-            if (CKPT && stash_slot >= 0 && act) {
+            if (CKPT && STASH && stash_slot >= 0 && act) {
                 float* const sp = P.stash_pool + (int64_t)stash_slot * P.stash_slot_floats;
                 const int jl = (j % K) * 64 + lane;
                 f32x4_t* const mp = reinterpret_cast<f32x4_t*>(sp + (int64_t)jl * (4 * CS::NM));
@@ -674,8 +676,8 @@ __device__ __forceinline__ void fwd_tile(const Ctx& P, int s, int tile, uint32_t
 
 // Dynamic LDS: waves_per_block x bitmap_words words (zero bitmap_words: no
 // union bitmap; mixed-voxel samples then walk one voxel group at a time).
-template <int CP, bool CKPT, bool STATS, bool PERSIST, bool LOSS = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP, CKPT, STATS, PERSIST), 8))) void k_render_fwd(Ctx P) {
+template <int CP, bool CKPT, bool STATS, bool PERSIST, bool LOSS = false, bool STASH = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP, CKPT, STATS, PERSIST, STASH), 8))) void k_render_fwd(Ctx P) {
     extern __shared__ uint32_t bm_all[];
     uint32_t* bm = nullptr;
     if (P.bitmap_words > 0) {
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FWD_WPE(CP,
     }
     for_each_tile<PERSIST>(P, [&](int t, const Ctx& Q) {
         const int s = find_scene(Q.desc, t);
-        fwd_tile<CP, CKPT, STATS, LOSS>(Q, s, t - Q.desc->s[s].tile_off, bm);
+        fwd_tile<CP, CKPT, STATS, LOSS, STASH>(Q, s, t - Q.desc->s[s].tile_off, bm);
     });
 }
 
@@ -1994,13 +1996,15 @@ static size_t km_lds_bytes(int words, int wpb, int CP) {
 template <int CP, bool LOSS>
 static void fwd_launch(const Ctx& P, const TuneDev& t, size_t shm, hipStream_t st) {
     const int wpb = t.waves_per_block;
-    const bool ck = P.ckpt != nullptr;
+    const bool ck = P.ckpt != nullptr, sth = ck && P.stash_tab != nullptr;
     if (t.persistent) {
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, P.queue, N_XCD * QUEUE_STRIDE, 0);
-        if (ck) launch_tiles(k_render_fwd<CP, true, false, true, LOSS>, true, P, wpb, shm, st);
+        if (sth) launch_tiles(k_render_fwd<CP, true, false, true, LOSS, true>, true, P, wpb, shm, st);
+        else if (ck) launch_tiles(k_render_fwd<CP, true, false, true, LOSS>, true, P, wpb, shm, st);
         else launch_tiles(k_render_fwd<CP, false, false, true, LOSS>, true, P, wpb, shm, st);
     } else {
-        if (ck) launch_tiles(k_render_fwd<CP, true, false, false, LOSS>, false, P, wpb, shm, st);
+        if (sth) launch_tiles(k_render_fwd<CP, true, false, false, LOSS, true>, false, P, wpb, shm, st);
+        else if (ck) launch_tiles(k_render_fwd<CP, true, false, false, LOSS>, false, P, wpb, shm, st);
         else launch_tiles(k_render_fwd<CP, false, false, false, LOSS>, false, P, wpb, shm, st);
     }
 }
@@ -2011,8 +2015,9 @@ static void fwd_run(const GridDev& g, const BatchDesc& d, const BatchIO& io, con
     prep_records<CP>(d, g, io, l, st);
     const int wpb = t.waves_per_block;
     Ctx P = P0;
-    // the stash serves only the primitive-major backward of this tuning
-    if (P.stash_tab && !(t.bwd_mode != 1 && bwd_primitive_major_ok(g, d.max_n, P.mr.K, wpb))) {
+    // the stash serves only the primitive-major backward of this tuning; the
+    // counting variant does not write it
+    if (P.stash_tab && (P.stats || !(t.bwd_mode != 1 && bwd_primitive_major_ok(g, d.max_n, P.mr.K, wpb)))) {
         P.stash_tab = nullptr;
         P.stash_pool = nullptr;
     }
