@@ -319,22 +319,23 @@ def _grads(b, n):
     return [{k[2:]: v.cpu().numpy() for k, v in b.scene_outputs(i).items() if k.startswith("g_")} for i in range(n)]
 
 
-@pytest.mark.parametrize("tw,K,C", [(8, 4, 5), (16, 8, 5), (8, 8, 3), (16, 8, 17), (8, 8, 32)])
-def test_stash_backward_matches_recompute_and_oracle(tw, K, C):
+@pytest.mark.parametrize("tw,K,C,ns", [(8, 4, 5, (30, 12, 40)), (16, 8, 5, (30, 12, 40)), (8, 8, 3, (30, 12, 40)),
+                                       (16, 8, 17, (30, 12, 40)), (8, 8, 32, (30, 12, 40)), (8, 8, 5, (30, 0, 40))])
+def test_stash_backward_matches_recompute_and_oracle(tw, K, C, ns):
     """A forward with checkpoints leaves a_j and the class sums in the stash;
     the backward then skips its first evaluation of each chunk's pairs.  The
     forward's outputs do not change (bit for bit), the slots asked for are one
     per chunk each tile entered, and the gradients match the recomputing
     backward and the oracle, with a full pool and with one that covers a
     third of the chunks (the rest recomputed)."""
-    scenes = _small_batch(seed=97, ns=(30, 12, 40), sizes=((24, 16), (9, 7), (16, 16)), C=C)
+    scenes = _small_batch(seed=97, ns=ns, sizes=((24, 16), (9, 7), (16, 16)), C=C)
     b = _make_batch(scenes, K=K)
     ups = _upstream(scenes, 98)
     for i, (gd, gs) in enumerate(ups):
         b.set_upstream(i, torch.from_numpy(gd).cuda(), torch.from_numpy(gs).cuda())
     tune = api.Tuning(tw, 2, 2, 1, K)
     b.build_index()
-    _say(f"stash: recompute, tile {tw}, chunk {K}, {C} classes")
+    _say(f"stash: recompute, tile {tw}, chunk {K}, {C} classes, primitives {ns}")
     b.render_fwd(tune)
     b.render_bwd(tune)
     torch.cuda.synchronize()
